@@ -1,0 +1,176 @@
+/*
+ * evd.h -- C ABI of the MI355X (gfx950) two-stage dense symmetric eigensolver.
+ *
+ * Problem (paper, Section 1; Algorithm 1, REQUIRE/ENSURE): for a dense
+ * symmetric A in R^{n x n} compute A = Q diag(W) Q^T with W the eigenvalues
+ * (ascending) and, if requested, Q the orthogonal eigenvector matrix.
+ *
+ * Method (paper, Sections 2.1 and 3.3): successive band reduction (SBR) of A
+ * to a band matrix B of half-bandwidth b with blocked Householder panels and
+ * the two-sided ZY update of Eq. 1; bulge chasing (BC) of B to a tridiagonal
+ * T; divide and conquer (D&C) on T; back transformation in the reordered
+ * stage order of Section 3.3 (SBR-back and BC-back applied to the identity,
+ * then one extra GEMM Q = Q_sb * Q_d).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are column-major; element (i, j) of M with leading dimension
+ *    ld is M[i + j*ld].  Sizes and leading dimensions are 64-bit.
+ *  - Pointers are DEVICE pointers (memory of the context's device) unless
+ *    marked [host].  The caller owns all buffers; the library allocates no
+ *    device memory inside compute calls (scratch comes from `work`).
+ *  - Calls are asynchronous on the context's stream (evd_set_stream); results
+ *    are valid after the stream is synchronised.  Numerical status goes to the
+ *    device integer `info` where present.
+ *  - Argument errors are detected on the host before any launch: the call
+ *    returns EVD_ERR_INVALID_ARG and evd_last_invalid_arg() gives the 1-based
+ *    position of the offending argument (LAPACK's -info convention).
+ *  - No call throws across the ABI.  One context per host thread.
+ */
+#ifndef EVD_H
+#define EVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct evd_ctx_s *evd_ctx_t;
+
+typedef enum {
+    EVD_OK = 0,
+    EVD_ERR_INVALID_ARG = 1,   /* see evd_last_invalid_arg()                  */
+    EVD_ERR_WORKSPACE = 2,     /* work buffer smaller than the queried size   */
+    EVD_ERR_HIP = 3,           /* a HIP runtime call failed                   */
+    EVD_ERR_NONFINITE = 4,     /* reserved: non-finite input                  */
+    EVD_ERR_NOT_CONVERGED = 5, /* reserved: host-visible non-convergence      */
+    EVD_ERR_NOT_IMPLEMENTED = 6
+} evd_status_t;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context bound to HIP device `device`.  [host] *ctx receives the
+ * handle.  The context owns only events and tunables.  device = -1 creates a
+ * validation-only context: every entry point checks its arguments as usual
+ * and then returns EVD_ERR_HIP without touching any device (for testing the
+ * argument checks on machines without a GPU). */
+evd_status_t evd_create(evd_ctx_t *ctx, int device);
+evd_status_t evd_destroy(evd_ctx_t ctx);
+
+/* Borrow a HIP stream (hipStream_t passed as void*; NULL = default stream). */
+evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
+
+/* Tunables ([host] key strings):
+ *   "b"            band half-width of SBR/BC, 0 = automatic (power of two, 4..64)
+ *   "bc_waves"     number of persistent bulge-chasing wavefronts, 0 = automatic
+ *   "order"        0 = reordered stages (paper Section 3.3), 1 = conventional order
+ *   "timing"       1 = record per-stage times (host-synchronising; for benchmarks)
+ * Unknown keys return EVD_ERR_INVALID_ARG. */
+evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value);
+evd_status_t evd_get_param(evd_ctx_t ctx, const char *key, int64_t *value /*[host]*/);
+
+/* 1-based index of the argument that made the last call fail, 0 if none. */
+int evd_last_invalid_arg(evd_ctx_t ctx);
+const char *evd_status_string(evd_status_t s);
+
+/* Per-stage wall times (ms) of the last evd_dsyevd call when "timing" = 1:
+ * [0] SBR, [1] BC, [2] D&C / eigenvalue solve, [3] SBR-back, [4] BC-back,
+ * [5] final GEMM, [6] total, [7] reserved.  [host] ms[8]. */
+evd_status_t evd_get_stage_times(evd_ctx_t ctx, float *ms);
+
+/* ------------------------------------------------------------------ GEMM */
+
+/* C = alpha * op(A) * op(B) + beta * C on FP64 matrix cores (MFMA).
+ * The products of Eq. 1 (Section 2.1.1), of SBR-back and of the final
+ * eigenvector GEMM Q = Q_sb * Q_d (Section 3.3) are all of this form.
+ *   opa: 'N' op(A) = A (m x k), 'T' op(A) = A^T (A is k x m),
+ *        'S' op(A) = the symmetric m x m matrix whose lower triangle is stored
+ *            in A (k must equal m; the strict upper triangle is not read).
+ *   opb: 'N' op(B) = B (k x n), 'T' op(B) = B^T (B is n x k).
+ *   lower_c: nonzero -> only entries C(i, j) with i >= j are written (SYR2K-style).
+ * `work` (may be NULL) is scratch for split-K partial sums; when it is NULL or
+ * smaller than evd_dgemm_work_size() the product runs without K splitting. */
+evd_status_t evd_dgemm(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_t m, int64_t n, int64_t k,
+                       double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                       double beta, double *C, int64_t ldc, void *work, size_t work_bytes);
+evd_status_t evd_dgemm_work_size(evd_ctx_t ctx, int64_t m, int64_t n, int64_t k, size_t *bytes /*[host]*/);
+
+/* ------------------------------------------------------------------ full EVD */
+
+/* dsyevd-style driver (LAPACK convention; paper Section 1).
+ *   jobz 'N': eigenvalues only -> W (ascending); A is destroyed.
+ *   jobz 'V': eigenvalues -> W and orthonormal eigenvectors -> A (column i
+ *             pairs with W[i]).
+ *   uplo 'L' or 'U': the triangle of A that is read.
+ *   A: n x n, lda >= max(1, n).  W: n doubles.  info: one device int32,
+ *   0 on success, > 0 if the tridiagonal solver did not converge.
+ *   work: at least evd_dsyevd_work_size() bytes, 256-byte aligned. */
+evd_status_t evd_dsyevd_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n, int64_t lda,
+                                  size_t *bytes /*[host]*/);
+evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda,
+                        double *W, void *work, size_t work_bytes, int32_t *info);
+
+/* ------------------------------------------------------------------ stages */
+
+/* Stage 1, SBR (Section 2.1.1, Fig. 1, Eq. 1): reduce the symmetric A (lower
+ * triangle read; 'U' is first mirrored into it) to a band matrix B of
+ * half-bandwidth b by panels of b columns: panel k is QR-factored,
+ * P_k = (I - Y_k T_k Y_k^T) R_k, and the trailing matrix A_2 receives
+ * Z = A_2 W - 1/2 Y (W^T A_2 W), A_2 <- A_2 - Y Z^T - Z Y^T with W = Y T.
+ * Outputs:
+ *   AB (ldab >= 2b+1, n columns): B in lower band storage, AB[d + j*ldab] =
+ *      B(j+d, j) for 0 <= d <= b; rows b+1..2b are zeroed (room for bulges).
+ *   A: columns kb..kb+b-1, rows (k+1)b..n-1 hold the explicit Y_k
+ *      (unit lower trapezoidal: ones on its diagonal, zeros above).
+ *   T: the b x b upper triangular T_k of panel k at T + k*b*b (column-major,
+ *      leading dimension b); evd_sbr_num_panels(n, b) panels.
+ * Requires 1 <= b <= 64, b | 64 (b in {1,2,4,8,16,32,64}). */
+int64_t evd_sbr_num_panels(int64_t n, int64_t b);
+evd_status_t evd_dsy2sb_work_size(evd_ctx_t ctx, int64_t n, int64_t b, size_t *bytes /*[host]*/);
+evd_status_t evd_dsy2sb(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda,
+                        double *AB, int64_t ldab, double *T, void *work, size_t work_bytes);
+
+/* Stage 2, BC (Section 2.1.1; Section 4.2 for its sweep/step structure):
+ * reduce the band matrix in AB to tridiagonal T = tridiag(e, d, e) by
+ * Householder bulge chasing.  Sweep c (0 <= c < n-2) annihilates column c
+ * below its sub-diagonal with a reflector on rows c+1..c+b and chases the
+ * bulge down in steps s = 1, 2, ...; step s acts on rows r = c+1+s*b ..
+ * r+b-1.  Reflector (c, s) is H = I - tau v v^T with v[0] = 1, stored at
+ *   V  [ (s*n + c) * b + i ],  i = 0..b-1 (zero-padded), and
+ *   TAU[  s*n + c ]             (0 for reflectors that do not exist),
+ * for s < evd_bc_num_steps(n, b).  T = H_m ... H_1 B H_1 ... H_m in
+ * generation order.  AB is overwritten.  V/TAU may be NULL when jobz = 'N'.
+ * work: evd_dsb2st_work_size() bytes (one progress counter per sweep). */
+int64_t evd_bc_num_steps(int64_t n, int64_t b);
+evd_status_t evd_dsb2st_work_size(evd_ctx_t ctx, int64_t n, size_t *bytes /*[host]*/);
+evd_status_t evd_dsb2st(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, int64_t ldab,
+                        double *d, double *e, double *V, double *TAU, void *work, size_t work_bytes);
+
+/* Stage 3, tridiagonal eigensolver on T = tridiag(e, d, e) (Section 2.1.1;
+ * divide and conquer of Cuppen / Gu-Eisenstat, Tisseur-Dongarra):
+ *   compz 'I': W (ascending) and eigenvectors of T in Z (n x n, ldz >= n).
+ *   compz 'N': eigenvalues only (Sturm bisection); Z is not referenced.
+ * d, e are not modified.  info: device int32, > 0 on non-convergence. */
+evd_status_t evd_dstedc_work_size(evd_ctx_t ctx, char compz, int64_t n, size_t *bytes /*[host]*/);
+evd_status_t evd_dstedc(evd_ctx_t ctx, char compz, int64_t n, const double *d, const double *e,
+                        double *W, double *Z, int64_t ldz, void *work, size_t work_bytes, int32_t *info);
+
+/* Stage 4a, SBR-back (Section 2.1.2; Algorithm 1 genW/genQ): form
+ * Q_s = (I - Y_0 T_0 Y_0^T)(I - Y_1 T_1 Y_1^T) ... in Q (n x n, ldq >= n),
+ * from the Y_k stored in A and the T_k in T by evd_dsy2sb. */
+evd_status_t evd_dorgsb_work_size(evd_ctx_t ctx, int64_t n, int64_t b, size_t *bytes /*[host]*/);
+evd_status_t evd_dorgsb(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T,
+                        double *Q, int64_t ldq, void *work, size_t work_bytes);
+
+/* Stage 4b, BC-back (Sections 2.1.2 and 4.3): Q <- Q H_1 H_2 ... H_m with
+ * the bulge-chasing reflectors of evd_dsb2st (rows of Q independent).
+ * Q is m_rows x n (ldq >= m_rows). */
+evd_status_t evd_dbcback(evd_ctx_t ctx, int64_t m_rows, int64_t n, int64_t b, const double *V,
+                         const double *TAU, double *Q, int64_t ldq);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVD_H */

@@ -1,0 +1,388 @@
+// FP64 GEMM on gfx950 matrix cores: C = alpha op(A) op(B) + beta C.
+//
+// Used for every dense product of the method: the panel products of the ZY
+// update (paper Eq. 1: A_2 W, W^T (A_2 W), Y M, and the rank-2b SYR2K
+// A_2 - Y Z^T - Z Y^T), SBR-back, the divide-and-conquer merge products and
+// the final eigenvector GEMM Q = Q_sb Q_d of the reordered stages (Sec. 3.3).
+//
+// Design: a workgroup computes a BM x BN tile of C with (BM/WM) x (BN/WN)
+// wavefronts; each wavefront owns a WM x WN sub-tile made of 16 x 16
+// accumulators of v_mfma_f64_16x16x4 (1024 FMAs per instruction).  K is
+// staged through LDS in slices of 16 with two buffers (one barrier per
+// slice; the global loads of slice t+1 are in flight while slice t is
+// multiplied).  The MFMA is issued with the B fragment as its first operand,
+// so each group of 16 lanes holds 16 consecutive rows of one column of C and
+// the stores are coalesced along the column-major C.  (Accumulator layout of
+// v_mfma_f64_16x16x4: lane l, element r holds D(l/16 + 4 r, l % 16).)
+//
+// op(A) can be A, A^T, or the symmetric matrix held in A's lower triangle
+// (tiles strictly below the diagonal are read directly, tiles strictly above
+// are read transposed from the mirror tile, diagonal tiles element-wise).
+#include "common.h"
+
+namespace {
+
+constexpr int BK = 16;
+constexpr int PAD = 1;
+
+template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
+__device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64_t kbeg, int64_t kend, int64_t m0,
+                                          int64_t n0, double alpha, const double *__restrict__ A, int64_t lda,
+                                          const double *__restrict__ B, int64_t ldb, double beta,
+                                          double *__restrict__ C, int64_t ldc)
+{
+    constexpr int NW = (BM / WM) * (BN / WN);
+    constexpr int NT = NW * 64;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int EA = BM * BK / NT;
+    constexpr int EB = BN * BK / NT;
+    static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile/thread mismatch");
+
+    __shared__ double As[2][BK][BM + PAD];
+    __shared__ double Bs[2][BK][BN + PAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % (BM / WM), wn = wave / (BM / WM);
+    (void)k;
+
+    double ra[EA], rb[EB];
+    int amap = 0;  // 0: row-fastest mapping, 1: k-fastest mapping (A slice)
+
+    auto load_a = [&](int64_t kt) {
+        if (OPA == OP_N) {
+            amap = 0;
+#pragma unroll
+            for (int r = 0; r < EA; ++r) {
+                const int e = tid + r * NT;
+                const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
+                ra[r] = (gi < m && gk < kend) ? A[gi + gk * lda] : 0.0;
+            }
+        } else if (OPA == OP_T) {
+            amap = 1;
+#pragma unroll
+            for (int r = 0; r < EA; ++r) {
+                const int e = tid + r * NT;
+                const int64_t gk = kt + (e % BK), gi = m0 + (e / BK);
+                ra[r] = (gi < m && gk < kend) ? A[gk + gi * lda] : 0.0;
+            }
+        } else {  // symmetric, lower triangle stored
+            if (m0 >= kt + BK - 1) {  // all rows >= all cols: read directly
+                amap = 0;
+#pragma unroll
+                for (int r = 0; r < EA; ++r) {
+                    const int e = tid + r * NT;
+                    const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
+                    ra[r] = (gi < m && gk < kend) ? A[gi + gk * lda] : 0.0;
+                }
+            } else if (m0 + BM - 1 <= kt) {  // all rows <= all cols: mirror
+                amap = 1;
+#pragma unroll
+                for (int r = 0; r < EA; ++r) {
+                    const int e = tid + r * NT;
+                    const int64_t gk = kt + (e % BK), gi = m0 + (e / BK);
+                    ra[r] = (gi < m && gk < kend) ? A[gk + gi * lda] : 0.0;
+                }
+            } else {
+                amap = 0;
+#pragma unroll
+                for (int r = 0; r < EA; ++r) {
+                    const int e = tid + r * NT;
+                    const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
+                    double v = 0.0;
+                    if (gi < m && gk < kend) v = (gi >= gk) ? A[gi + gk * lda] : A[gk + gi * lda];
+                    ra[r] = v;
+                }
+            }
+        }
+    };
+    auto store_a = [&](int buf) {
+        if (amap == 0) {
+#pragma unroll
+            for (int r = 0; r < EA; ++r) {
+                const int e = tid + r * NT;
+                As[buf][e / BM][e % BM] = ra[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < EA; ++r) {
+                const int e = tid + r * NT;
+                As[buf][e % BK][e / BK] = ra[r];
+            }
+        }
+    };
+    auto load_b = [&](int64_t kt) {
+        if (OPB == OP_N) {
+#pragma unroll
+            for (int r = 0; r < EB; ++r) {
+                const int e = tid + r * NT;
+                const int64_t gk = kt + (e % BK), gj = n0 + (e / BK);
+                rb[r] = (gj < n && gk < kend) ? B[gk + gj * ldb] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < EB; ++r) {
+                const int e = tid + r * NT;
+                const int64_t gj = n0 + (e % BN), gk = kt + (e / BN);
+                rb[r] = (gj < n && gk < kend) ? B[gj + gk * ldb] : 0.0;
+            }
+        }
+    };
+    auto store_b = [&](int buf) {
+        if (OPB == OP_N) {
+#pragma unroll
+            for (int r = 0; r < EB; ++r) {
+                const int e = tid + r * NT;
+                Bs[buf][e % BK][e / BK] = rb[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < EB; ++r) {
+                const int e = tid + r * NT;
+                Bs[buf][e / BN][e % BN] = rb[r];
+            }
+        }
+    };
+
+    double4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+    const int64_t nkt = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+    if (nkt > 0) {
+        load_a(kbeg);
+        load_b(kbeg);
+        store_a(0);
+        store_b(0);
+        __syncthreads();
+        const int lr = lane & 15, lk = lane >> 4;
+        for (int64_t t = 0; t < nkt; ++t) {
+            const int cur = (int)(t & 1);
+            if (t + 1 < nkt) {
+                load_a(kbeg + (t + 1) * BK);
+                load_b(kbeg + (t + 1) * BK);
+            }
+#pragma unroll
+            for (int k4 = 0; k4 < BK; k4 += 4) {
+                double fa[TM], fb[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) fa[i] = As[cur][k4 + lk][wm * WM + i * 16 + lr];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) fb[j] = Bs[cur][k4 + lk][wn * WN + j * 16 + lr];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i], acc[i][j], 0, 0, 0);
+            }
+            if (t + 1 < nkt) {
+                store_a(cur ^ 1);
+                store_b(cur ^ 1);
+            }
+            __syncthreads();
+        }
+    }
+
+    // epilogue: lane holds C(i0 + lane%16, j0 + lane/16 + 4 r), r = 0..3
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int64_t gi = m0 + wm * WM + i * 16 + lr;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gj = n0 + wn * WN + j * 16 + lq + 4 * r;
+                if (gi < m && gj < n && (!LOWER || gi >= gj)) {
+                    double v = alpha * acc[i][j][r];
+                    double *cp = &C[gi + gj * ldc];
+                    if (beta != 0.0) v += beta * (*cp);
+                    *cp = v;
+                }
+            }
+        }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(
+    int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
+    int64_t split_stride)
+{
+    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    if (LOWER && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
+    gemm_body<BM, BN, WM, WN, OPA, OPB, LOWER>(m, n, k, kbeg, kend, m0, n0, alpha, A, lda, B, ldb, beta,
+                                               C + (int64_t)blockIdx.z * split_stride, ldc);
+}
+
+// Grouped product with sizes in device memory: problem blockIdx.z, C = A B
+// (op N, N); tiles outside the problem exit.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_grouped_kernel(const GemmProblem *probs)
+{
+    const GemmProblem p = probs[blockIdx.z];
+    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    if (m0 >= p.m || n0 >= p.n) return;
+    gemm_body<BM, BN, WM, WN, OP_N, OP_N, 0>(p.m, p.n, p.k, 0, p.k, m0, n0, 1.0, p.A, p.lda, p.B, p.ldb, 0.0, p.C,
+                                             p.ldc);
+}
+
+__global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const double *__restrict__ P, int64_t stride,
+                                     double alpha, double beta, double *__restrict__ C, int64_t ldc, int lower)
+{
+    const int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % m, j = idx / m;
+        if (lower && i < j) continue;
+        double s = 0.0;
+        for (int z = 0; z < splits; ++z) s += P[z * stride + i + j * m];
+        double *cp = &C[i + j * ldc];
+        double v = alpha * s;
+        if (beta != 0.0) v += beta * (*cp);
+        *cp = v;
+    }
+}
+
+template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
+void launch_cfg(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha,
+                const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                int64_t split_stride)
+{
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, OPA, OPB, LOWER>), grid, dim3(NT), 0, s, m, n, k, kchunk,
+                       alpha, A, lda, B, ldb, beta, C, ldc, split_stride);
+}
+
+template <int BM, int BN, int WM, int WN>
+void launch_ops(hipStream_t s, int opa, int opb, int lower, dim3 grid, int64_t m, int64_t n, int64_t k,
+                int64_t kchunk, double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                double beta, double *C, int64_t ldc, int64_t split_stride)
+{
+#define EVD_GEMM_CASE(OA, OB, LW)                                                                          \
+    if (opa == OA && opb == OB && lower == LW) {                                                          \
+        launch_cfg<BM, BN, WM, WN, OA, OB, LW>(s, grid, m, n, k, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, \
+                                               split_stride);                                             \
+        return;                                                                                           \
+    }
+    EVD_GEMM_CASE(OP_N, OP_N, 0)
+    EVD_GEMM_CASE(OP_N, OP_T, 0)
+    EVD_GEMM_CASE(OP_T, OP_N, 0)
+    EVD_GEMM_CASE(OP_T, OP_T, 0)
+    EVD_GEMM_CASE(OP_S, OP_N, 0)
+    EVD_GEMM_CASE(OP_S, OP_T, 0)
+    EVD_GEMM_CASE(OP_N, OP_N, 1)
+    EVD_GEMM_CASE(OP_N, OP_T, 1)
+    EVD_GEMM_CASE(OP_T, OP_N, 1)
+    EVD_GEMM_CASE(OP_T, OP_T, 1)
+#undef EVD_GEMM_CASE
+}
+
+struct GemmPlan {
+    int bm, bn, splits;
+    int64_t kchunk;
+};
+
+GemmPlan plan_gemm(int64_t m, int64_t n, int64_t k, size_t ws_elems)
+{
+    GemmPlan p;
+    p.bm = (m > 64) ? 128 : 64;
+    p.bn = (n > 64) ? 128 : 64;
+    int64_t tiles = evd_ceil_div(m, p.bm) * evd_ceil_div(n, p.bn);
+    if (tiles < 512 && p.bm == 128 && p.bn == 128) {
+        // prefer more, smaller tiles when the grid is small
+        if (m >= n) p.bn = 64; else p.bm = 64;
+        tiles = evd_ceil_div(m, p.bm) * evd_ceil_div(n, p.bn);
+    }
+    p.splits = 1;
+    p.kchunk = k;
+    // split K when the output grid cannot fill the chip and K is long
+    if (tiles < 256 && k >= 1024) {
+        int64_t want = evd_ceil_div(512, tiles);
+        int64_t maxs = k / 256;
+        int64_t sp = want < maxs ? want : maxs;
+        if (sp > 64) sp = 64;
+        if (sp >= 2 && (size_t)(sp * m * n) <= ws_elems) {
+            p.kchunk = evd_ceil_div(evd_ceil_div(k, sp), BK) * BK;
+            p.splits = (int)evd_ceil_div(k, p.kchunk);
+        }
+    }
+    return p;
+}
+
+}  // namespace
+
+evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob, int64_t max_m, int64_t max_n)
+{
+    if (nprob <= 0 || max_m <= 0 || max_n <= 0) return EVD_OK;
+    if (nprob > 65535) return EVD_ERR_INVALID_ARG;
+    if (max_m > 64 && max_n > 64 && max_m * max_n >= (int64_t)512 * 128 * 128) {
+        dim3 grid((unsigned)evd_ceil_div(max_m, 128), (unsigned)evd_ceil_div(max_n, 128), (unsigned)nprob);
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, probs);
+    } else {
+        dim3 grid((unsigned)evd_ceil_div(max_m, 64), (unsigned)evd_ceil_div(max_n, 64), (unsigned)nprob);
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<64, 64, 32, 32>), grid, dim3(256), 0, s, probs);
+    }
+    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+}
+
+size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k)
+{
+    GemmPlan p = plan_gemm(m, n, k, (size_t)-1);
+    return p.splits > 1 ? (size_t)p.splits * (size_t)m * (size_t)n : 0;
+}
+
+evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, int64_t n, int64_t k, double alpha,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,
+                      int64_t ldc, double *ws, size_t ws_elems)
+{
+    if (m <= 0 || n <= 0) return EVD_OK;
+    if (k <= 0 || alpha == 0.0) {
+        // C = beta C on the referenced part
+        if (beta == 1.0) return EVD_OK;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)evd_ceil_div(m * n, 256 * 4) < 65535
+                                                          ? (unsigned)evd_ceil_div(m * n, 256 * 4) : 65535u),
+                           dim3(256), 0, s, m, n, 0, (const double *)nullptr, (int64_t)0, 0.0, beta, C, ldc,
+                           lower_c);
+        return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    }
+    GemmPlan p = plan_gemm(m, n, k, ws ? ws_elems : 0);
+    const int lower = lower_c ? 1 : 0;
+    dim3 grid((unsigned)evd_ceil_div(m, p.bm), (unsigned)evd_ceil_div(n, p.bn), (unsigned)p.splits);
+    double *Cout = C;
+    int64_t ldo = ldc, sstride = 0;
+    double a = alpha, bta = beta;
+    if (p.splits > 1) {
+        Cout = ws;
+        ldo = m;
+        sstride = m * n;
+        a = 1.0;
+        bta = 0.0;
+    }
+    if (p.bm == 128 && p.bn == 128)
+        launch_ops<128, 128, 64, 64>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
+                                     sstride);
+    else if (p.bm == 128 && p.bn == 64)
+        launch_ops<128, 64, 64, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
+                                    sstride);
+    else if (p.bm == 64 && p.bn == 128)
+        launch_ops<64, 128, 32, 64>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
+                                    sstride);
+    else
+        launch_ops<64, 64, 32, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
+                                   sstride);
+    if (hipGetLastError() != hipSuccess) return EVD_ERR_HIP;
+    if (p.splits > 1) {
+        int64_t blocks = evd_ceil_div(m * n, 256);
+        if (blocks > 65535) blocks = 65535;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, n, p.splits, ws,
+                           sstride, alpha, beta, C, ldc, lower);
+        if (hipGetLastError() != hipSuccess) return EVD_ERR_HIP;
+    }
+    return EVD_OK;
+}

@@ -1,0 +1,371 @@
+// Stage 1: successive band reduction (SBR), paper Section 2.1.1, Fig. 1, Eq. 1.
+//
+// For panel k (columns j0 = k b .. j0+b-1, rows i0 = j0+b .. n-1, m = n-i0):
+//   1. panel QR  P_k = (I - Y T Y^T) R  (cooperative kernel below);
+//   2. W = Y T;  X = A_2 W (symmetric A_2 read from its lower triangle);
+//      M = W^T X;  Z = X - 1/2 Y M                          (Eq. 1, first line)
+//   3. A_2 <- A_2 - Y Z^T - Z Y^T as ONE rank-2b product [Y Z][Z Y]^T on the
+//      lower triangle                                        (Eq. 1, second line)
+// The updated trailing matrix is the next panel's input (Section 2.1.1).
+//
+// Panel QR: the m x b panel is split into row chunks, one workgroup per chunk
+// holding its rows in LDS for the whole factorization.  Column j needs two
+// chip-wide reductions (its norm, then v^T P for the remaining columns plus
+// Y^T v for the T factor); they are separated by grid barriers of a
+// cooperative launch.  The T factor (forward, column-wise:
+// T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T v_j)) is formed at the end by
+// workgroup 0 from the reduced Y^T v products.
+#include <hip/hip_cooperative_groups.h>
+
+#include "common.h"
+
+namespace cg = cooperative_groups;
+
+namespace {
+
+constexpr int PANEL_THREADS = 256;
+
+__global__ void fill_kernel(double *p, int64_t count, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// A(i, j) <- A(j, i) for i > j  (mirror the stored upper triangle into the lower)
+__global__ void mirror_upper_kernel(int64_t n, double *A, int64_t lda)
+{
+    const int64_t j = blockIdx.y;
+    for (int64_t i = j + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        A[i + j * lda] = A[j + i * lda];
+}
+
+// Copy the lower part of the diagonal blocks of the band into AB:
+// column j of panel block kb = (j / b) b covers rows j .. min(kb + b, n) - 1;
+// columns of the final (tail) block extend to row n - 1.
+__global__ void extract_diag_blocks_kernel(int64_t n, int64_t b, int64_t tail0, const double *A, int64_t lda,
+                                           double *AB, int64_t ldab)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+    if (j >= n) return;
+    int64_t limit = (j >= tail0) ? n : ((j / b) * b + b);
+    if (limit > n) limit = n;
+    for (int64_t d = threadIdx.x; j + d < limit; d += blockDim.x) AB[d + j * ldab] = A[j + d + j * lda];
+}
+
+template <int B>
+__global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, double *P, int64_t lda,
+                                                                 double *YZY, int64_t ldy, double *part,
+                                                                 double *Sg, double *taus, double *Tout,
+                                                                 double *AB, int64_t ldab, int64_t j0)
+{
+    // part layout (G workgroups): [0, G) norms; [G] x0; [G+1, G+1+B) reduced
+    // dots w; then B*G partial dots, column-major by column q: part[D0 + q*G + g].
+    extern __shared__ double smem[];
+    const int ldp = chunk + 1;
+    double *Ps = smem;                 // Ps[q * ldp + i]: panel column q, local row i
+    __shared__ double wsh[B];
+    __shared__ double red[PANEL_THREADS / 64];
+    __shared__ double betas[B];
+    __shared__ double scal[4];
+
+    cg::grid_group grid = cg::this_grid();
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    const int64_t r0 = (int64_t)g * chunk;
+    const int rows = (int)((m - r0) < chunk ? (m - r0) : chunk);
+    const int nr = (int)(m < B ? m : B);
+    double *partN = part, *partX0 = part + G, *partW = part + G + 1, *partD = part + G + 1 + B;
+
+    for (int e = tid; e < rows * B; e += PANEL_THREADS) {
+        const int i = e % rows, q = e / rows;
+        Ps[q * ldp + i] = P[(r0 + i) + (int64_t)q * lda];
+    }
+    __syncthreads();
+
+    constexpr int TPC = PANEL_THREADS / B;  // threads per column in the dot phase
+    for (int j = 0; j < nr; ++j) {
+        // ---- phase 1: partial sum of squares below row j
+        double ss = 0.0;
+        for (int i = tid; i < rows; i += PANEL_THREADS)
+            if (r0 + i > j) { const double x = Ps[j * ldp + i]; ss += x * x; }
+        ss = block_sum(ss, red);
+        if (tid == 0) {
+            partN[g] = ss;
+            if (g == 0) partX0[0] = Ps[j * ldp + j];  // row j lives in chunk 0
+        }
+        __threadfence();
+        grid.sync();
+
+        // ---- phase 2: Householder vector of column j, partial dots
+        double sig = 0.0;
+        for (int h = tid; h < G; h += PANEL_THREADS) sig += partN[h];
+        sig = block_sum(sig, red);
+        if (tid == 0) {
+            const double x0 = partX0[0];
+            double tau = 0.0, beta = x0, scale = 0.0;
+            if (sig != 0.0) {
+                const double nrm = sqrt(x0 * x0 + sig);
+                beta = (x0 >= 0.0) ? -nrm : nrm;
+                tau = (beta - x0) / beta;
+                scale = 1.0 / (x0 - beta);
+            }
+            scal[0] = tau;
+            scal[1] = beta;
+            scal[2] = scale;
+        }
+        __syncthreads();
+        const double tau = scal[0], scale = scal[2];
+        for (int i = tid; i < rows; i += PANEL_THREADS) {
+            const int64_t gi = r0 + i;
+            if (gi > j) Ps[j * ldp + i] *= scale;
+            else if (gi == j) Ps[j * ldp + i] = 1.0;
+        }
+        if (g == 0 && tid == 0) betas[j] = scal[1];
+        __syncthreads();
+        {
+            const int q = tid % B, sub = tid / B;
+            double acc = 0.0;
+            if (q != j)
+                for (int i = sub; i < rows; i += TPC)
+                    if (r0 + i >= j) acc += Ps[j * ldp + i] * Ps[q * ldp + i];
+            Ps[B * ldp + tid] = acc;  // scratch after the panel columns
+            __syncthreads();
+            if (tid < B) {
+                double s = 0.0;
+                for (int t = 0; t < TPC; ++t) s += Ps[B * ldp + tid + t * B];
+                partD[(int64_t)tid * G + g] = s;
+            }
+        }
+        __threadfence();
+        grid.sync();
+
+        // ---- phase 3a: workgroup g reduces the partial dots of columns g, g+G, ...
+        for (int q = g; q < B; q += G) {
+            double s = 0.0;
+            for (int h = tid; h < G; h += PANEL_THREADS) s += partD[(int64_t)q * G + h];
+            s = block_sum(s, red);
+            if (tid == 0) partW[q] = s;
+        }
+        __threadfence();
+        grid.sync();
+
+        // ---- phase 3b: update the remaining columns of the chunk
+        if (tid < B) {
+            const double s = partW[tid];
+            wsh[tid] = s;
+            if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = s;  // (Y[:, 0:j]^T v_j)
+        }
+        if (g == 0 && tid == 0) taus[j] = tau;
+        __syncthreads();
+        if (tau != 0.0) {
+            const int ncols = B - j - 1;
+            for (int e = tid; e < rows * ncols; e += PANEL_THREADS) {
+                const int i = e % rows, q = j + 1 + e / rows;
+                if (r0 + i >= j) Ps[q * ldp + i] -= tau * Ps[j * ldp + i] * wsh[q];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write back: explicit Y into the panel of A and into [Y | Z | Y]
+    for (int e = tid; e < rows * B; e += PANEL_THREADS) {
+        const int i = e % rows, q = e / rows;
+        const int64_t gi = r0 + i;
+        double y = 0.0;
+        if (q < nr) y = (gi > q) ? Ps[q * ldp + i] : (gi == q ? 1.0 : 0.0);
+        P[gi + (int64_t)q * lda] = y;
+        YZY[gi + (int64_t)q * ldy] = y;
+        YZY[gi + (int64_t)(2 * B + q) * ldy] = y;
+    }
+    if (g != 0) return;
+    // R (upper trapezoid of the first nr rows) -> band storage
+    for (int e = tid; e < B * B; e += PANEL_THREADS) {
+        const int p = e % B, q = e / B;
+        if (p <= q) {
+            const double v = (p >= nr) ? 0.0 : ((p == q) ? betas[q] : Ps[q * ldp + p]);
+            AB[(B + p - q) + (j0 + q) * ldab] = v;
+        }
+    }
+    __syncthreads();
+    // T factor in LDS (reuse the panel area), then out
+    double *Ts = smem;
+    for (int e = tid; e < B * B; e += PANEL_THREADS) Ts[e] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < B; ++j) {
+        const double tj = (j < nr) ? taus[j] : 0.0;
+        if (tid < j) {
+            double s = 0.0;
+            for (int r = tid; r < j; ++r) s += Ts[tid + r * B] * Sg[r + (int64_t)j * B];
+            Ts[tid + j * B] = -tj * s;
+        }
+        if (tid == 0) Ts[j + j * B] = tj;
+        __syncthreads();
+    }
+    for (int e = tid; e < B * B; e += PANEL_THREADS) Tout[e] = Ts[e];
+}
+
+template <int B>
+evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, double *P, int64_t lda, double *YZY, int64_t ldy, double *part,
+                          double *Sg, double *taus, double *Tout, double *AB, int64_t ldab, int64_t j0)
+{
+    int maxg = 256;
+    int64_t chunk = evd_ceil_div(m, maxg);
+    if (chunk < B) chunk = B;
+    chunk = evd_ceil_div(chunk, 16) * 16;
+    int G = (int)evd_ceil_div(m, chunk);
+    // LDS: B columns plus one scratch column of PANEL_THREADS doubles
+    int64_t ldp = chunk + 1;
+    size_t lds = (size_t)(B * ldp + (ldp > PANEL_THREADS ? ldp : PANEL_THREADS)) * sizeof(double);
+    if (lds < (size_t)B * B * sizeof(double)) lds = (size_t)B * B * sizeof(double);
+    if (lds > 150 * 1024) return EVD_ERR_INVALID_ARG;
+    int chunk_i = (int)chunk;
+    void *args[] = {&m, &chunk_i, &P, (void *)&lda, &YZY, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
+                    (void *)&ldab, (void *)&j0};
+    hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B>, dim3(G), dim3(PANEL_THREADS), args,
+                                              (unsigned)lds, ctx->stream);
+    return e == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+}
+
+evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, double *P, int64_t lda, double *YZY, int64_t ldy,
+                            double *part, double *Sg, double *taus, double *Tout, double *AB, int64_t ldab,
+                            int64_t j0)
+{
+    switch (b) {
+    case 1: return launch_panel<1>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    case 2: return launch_panel<2>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    case 4: return launch_panel<4>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    case 8: return launch_panel<8>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    case 16: return launch_panel<16>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    case 32: return launch_panel<32>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    case 64: return launch_panel<64>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    default: return EVD_ERR_INVALID_ARG;
+    }
+}
+
+struct SbrWork {
+    double *YZY;   // n x 3b
+    double *X;     // unused (Z is formed in place)
+    double *W;     // n x b
+    double *M;     // b x b
+    double *part;  // (257) x (b + 1)
+    double *Sg;    // b x b
+    double *taus;  // b
+    double *gemm_ws;
+    size_t gemm_ws_elems;
+};
+
+size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork *w)
+{
+    size_t off = 0;
+    auto take = [&](size_t elems) {
+        char *p = base ? base + off : nullptr;
+        off += evd_align256(elems * sizeof(double));
+        return (double *)p;
+    };
+    SbrWork t;
+    t.YZY = take((size_t)n * 3 * b);
+    t.W = take((size_t)n * b);
+    t.M = take((size_t)b * b);
+    t.part = take((size_t)256 + 1 + b + (size_t)b * 256 + 64);
+    t.Sg = take((size_t)b * b);
+    t.taus = take((size_t)b);
+    t.X = nullptr;
+    // split-K workspace for the b x b product W^T Z (K up to n)
+    size_t ws = gemm_splitk_ws_elems(b, b, n);
+    size_t ws2 = gemm_splitk_ws_elems(n, b, n);
+    if (ws2 > ws) ws = ws2;
+    t.gemm_ws = take(ws);
+    t.gemm_ws_elems = ws;
+    if (w) *w = t;
+    return off;
+}
+
+}  // namespace
+
+evd_status_t sbr_run(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda, double *AB,
+                     int64_t ldab, double *T, void *work)
+{
+    hipStream_t s = ctx->stream;
+    SbrWork w;
+    sbr_layout(n, b, (char *)work, &w);
+    if (uplo == 'U' || uplo == 'u') {
+        dim3 grid((unsigned)evd_ceil_div(n, 256) < 64 ? (unsigned)evd_ceil_div(n, 256) : 64u, (unsigned)n);
+        hipLaunchKernelGGL(mirror_upper_kernel, grid, dim3(256), 0, s, n, A, lda);
+    }
+    {
+        const int64_t cnt = ldab * n;
+        hipLaunchKernelGGL(fill_kernel, dim3((unsigned)(evd_ceil_div(cnt, 256) < 4096 ? evd_ceil_div(cnt, 256) : 4096)),
+                           dim3(256), 0, s, AB, cnt, 0.0);
+    }
+    const int64_t p = evd_sbr_num_panels(n, b);
+    for (int64_t k = 0; k < p; ++k) {
+        const int64_t j0 = k * b, i0 = j0 + b, m = n - i0;
+        double *P = A + i0 + j0 * lda;
+        double *A2 = A + i0 + i0 * lda;
+        double *Tk = T + k * b * b;
+        const int64_t ldy = m;
+        EVD_CHECK(panel_dispatch(ctx, b, m, P, lda, w.YZY, ldy, w.part, w.Sg, w.taus, Tk, AB, ldab, j0));
+        double *Y = w.YZY, *Zs = w.YZY + b * ldy;
+        // W = Y T
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, m, b, b, 1.0, Y, ldy, Tk, b, 0.0, w.W, m, nullptr, 0));
+        // X = A_2 W  (into the Z slot)
+        EVD_CHECK(gemm_f64(s, OP_S, OP_N, 0, m, b, m, 1.0, A2, lda, w.W, m, 0.0, Zs, ldy, w.gemm_ws,
+                           w.gemm_ws_elems));
+        // M = W^T X
+        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, b, b, m, 1.0, w.W, m, Zs, ldy, 0.0, w.M, b, w.gemm_ws,
+                           w.gemm_ws_elems));
+        // Z = X - 1/2 Y M
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, m, b, b, -0.5, Y, ldy, w.M, b, 1.0, Zs, ldy, nullptr, 0));
+        // A_2 <- A_2 - [Y Z] [Z Y]^T   (lower triangle)
+        EVD_CHECK(gemm_f64(s, OP_N, OP_T, 1, m, m, 2 * b, -1.0, w.YZY, ldy, Zs, ldy, 1.0, A2, lda, nullptr, 0));
+    }
+    {
+        dim3 blk(64, 4);
+        hipLaunchKernelGGL(extract_diag_blocks_kernel, dim3((unsigned)evd_ceil_div(n, 4)), blk, 0, s, n, b, p * b,
+                           (const double *)A, lda, AB, ldab);
+    }
+    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+}
+
+size_t sbr_work_bytes(int64_t n, int64_t b) { return sbr_layout(n, b, nullptr, nullptr); }
+
+extern "C" {
+
+int64_t evd_sbr_num_panels(int64_t n, int64_t b)
+{
+    if (b <= 0 || n < b + 2) return 0;
+    return (n - b - 2) / b + 1;
+}
+
+evd_status_t evd_dsy2sb_work_size(evd_ctx_t ctx, int64_t n, int64_t b, size_t *bytes)
+{
+    if (!ctx || !bytes) return EVD_ERR_INVALID_ARG;
+    if (n < 0) { ctx->last_invalid_arg = 2; return EVD_ERR_INVALID_ARG; }
+    if (b < 1 || b > 64 || (64 % b) != 0) { ctx->last_invalid_arg = 3; return EVD_ERR_INVALID_ARG; }
+    *bytes = sbr_work_bytes(n, b);
+    return EVD_OK;
+}
+
+evd_status_t evd_dsy2sb(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda, double *AB,
+                        int64_t ldab, double *T, void *work, size_t work_bytes)
+{
+    if (!ctx) return EVD_ERR_INVALID_ARG;
+    int bad = 0;
+    if (!(uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u')) bad = 2;
+    else if (n < 0) bad = 3;
+    else if (b < 1 || b > 64 || (64 % b) != 0) bad = 4;
+    else if (n > 0 && !A) bad = 5;
+    else if (lda < (n > 1 ? n : 1)) bad = 6;
+    else if (n > 0 && !AB) bad = 7;
+    else if (ldab < 2 * b + 1) bad = 8;
+    else if (evd_sbr_num_panels(n, b) > 0 && !T) bad = 9;
+    else if (n > 0 && !work) bad = 10;
+    else if (work_bytes < sbr_work_bytes(n, b)) bad = 11;
+    ctx->last_invalid_arg = bad;
+    if (bad) return bad == 11 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
+    if (n == 0) return EVD_OK;
+    if (ctx->device < 0) return EVD_ERR_HIP;
+    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    return sbr_run(ctx, uplo, n, b, A, lda, AB, ldab, T, work);
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+"""FP64 MFMA GEMM vs plain FP64 numpy products (through the C ABI)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(x):
+    return torch.from_numpy(np.asfortranarray(x).T.copy()).cuda()  # memory = column-major x
+
+
+def host(t, m, n):
+    return t.cpu().numpy().T[:m, :n]
+
+
+def cm_empty(m, n):
+    return torch.zeros((max(n, 1), max(m, 1)), dtype=torch.float64, device="cuda")
+
+
+CASES = [
+    ("N", "N", 0, 1, 1, 1), ("N", "N", 0, 17, 5, 3), ("N", "T", 0, 130, 70, 33), ("T", "N", 0, 64, 64, 64),
+    ("T", "T", 0, 129, 257, 100), ("N", "N", 0, 300, 200, 1000), ("S", "N", 0, 200, 64, 200),
+    ("S", "T", 0, 333, 40, 333), ("N", "T", 1, 300, 300, 128), ("N", "N", 1, 129, 129, 17),
+    ("T", "N", 0, 64, 64, 5000), ("N", "N", 0, 2048, 64, 2048), ("S", "N", 0, 1000, 64, 1000),
+]
+
+
+@pytest.mark.parametrize("opa,opb,lower,m,n,k", CASES)
+def test_dgemm_matches_fp64(opa, opb, lower, m, n, k):
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    Ash = (m, k) if opa == "N" else ((k, m) if opa == "T" else (m, m))
+    Bsh = (k, n) if opb == "N" else (n, k)
+    A = rng.standard_normal(Ash)
+    B = rng.standard_normal(Bsh)
+    C0 = rng.standard_normal((m, n))
+    alpha, beta = -0.75, 0.5
+    if opa == "S":
+        Afull = np.tril(A) + np.tril(A, -1).T
+        A_for = np.tril(A) + np.triu(np.full_like(A, np.nan), 1)  # upper triangle must not be read
+        opA = Afull
+    else:
+        A_for = A
+        opA = A if opa == "N" else A.T
+    opB = B if opb == "N" else B.T
+    ref = alpha * (opA @ opB) + beta * C0
+    dA, dB, dC = dev(A_for), dev(B), dev(C0)
+    wb = ctx.evd_dgemm_work_size(m, n, k)
+    work = torch.empty(max(wb // 8, 1), dtype=torch.float64, device="cuda")
+    ctx.evd_dgemm(opa, opb, lower, m, n, k, alpha, dA, A_for.shape[0], dB, B.shape[0], beta, dC, m, work, wb)
+    torch.cuda.synchronize()
+    out = host(dC, m, n)
+    scale = np.abs(opA).max() * np.abs(opB).max() * k + np.abs(C0).max()
+    tol = 4 * k * np.finfo(float).eps * scale + 1e-300
+    if lower:
+        mask = np.tril(np.ones((m, n), bool))
+        assert np.max(np.abs(out[mask] - ref[mask])) <= tol
+        assert np.array_equal(out[~mask], C0[~mask])  # strict upper untouched
+    else:
+        assert np.max(np.abs(out - ref)) <= tol
+
+
+def test_dgemm_no_workspace_equals_splitk():
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    rng = np.random.default_rng(3)
+    m, n, k = 64, 64, 8192
+    A, B = rng.standard_normal((k, m)), rng.standard_normal((k, n))
+    ref = A.T @ B
+    for use_ws in (False, True):
+        dC = cm_empty(m, n)
+        wb = ctx.evd_dgemm_work_size(m, n, k) if use_ws else 0
+        work = torch.empty(max(wb // 8, 1), dtype=torch.float64, device="cuda") if use_ws else None
+        ctx.evd_dgemm("T", "N", 0, m, n, k, 1.0, dev(A), k, dev(B), k, 0.0, dC, m, work, wb)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(host(dC, m, n) - ref)) <= 4 * k * 2.2e-16 * 20

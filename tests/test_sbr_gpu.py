@@ -1,0 +1,82 @@
+"""Stage 1 (SBR, Eq. 1) on the GPU: band eigenvalues vs the oracle, and the
+returned panel reflectors reproduce A = Q_s B Q_s^T."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.metrics as M
+from paper_2511_16174_amd import workloads as W
+from tests.gpu_helpers import band_to_dense, from_dev, to_dev, work_dev, zeros_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def run_sbr(A, b, uplo="L"):
+    from paper_2511_16174_amd import evd
+    import torch
+    ctx = evd.context(0)
+    n = A.shape[0]
+    ldab = 2 * b + 1
+    dA = to_dev(A)
+    dAB = zeros_dev(ldab * n)
+    p = evd.evd_sbr_num_panels(n, b)
+    dT = zeros_dev(max(p, 1) * b * b)
+    wb = ctx.evd_dsy2sb_work_size(n, b)
+    work = work_dev(wb)
+    ctx.evd_dsy2sb(uplo, n, b, dA, n, dAB, ldab, dT, work, wb)
+    torch.cuda.synchronize()
+    AB = from_dev(dAB, ldab, n)
+    Aout = from_dev(dA, n, n)
+    T = dT.cpu().numpy()[: p * b * b].reshape(p, b, b).transpose(0, 2, 1) if p else np.zeros((0, b, b))
+    return AB, Aout, T, p
+
+
+def q_from_panels(Aout, T, n, b, p):
+    Q = np.eye(n)
+    for k in range(p):
+        i0 = (k + 1) * b
+        Y = Aout[i0:, k * b:(k + 1) * b]
+        H = np.eye(n)
+        H[i0:, i0:] -= Y @ T[k] @ Y.T
+        Q = Q @ H
+    return Q
+
+
+@pytest.mark.parametrize("n,b", [(3, 1), (10, 4), (66, 64), (67, 64), (100, 8), (256, 16), (333, 32),
+                                 (512, 32), (300, 64), (130, 2)])
+def test_sbr_band_and_reflectors(n, b):
+    A = W.gaussian_sym(n, seed=n + b)
+    AB, Aout, T, p = run_sbr(A, b)
+    ldab = 2 * b + 1
+    assert np.all(AB[b + 1:, :] == 0.0)
+    B = band_to_dense(AB, n, b, ldab)
+    w_ref = oracle.syev(A, jobz="N")
+    assert M.eig_error(np.linalg.eigvalsh(B), w_ref) <= 1e-13
+    # T_k upper triangular, Y_k unit lower trapezoidal
+    for k in range(p):
+        assert np.all(np.tril(T[k], -1) == 0.0)
+        i0 = (k + 1) * b
+        Y = Aout[i0:, k * b:(k + 1) * b]
+        r = min(Y.shape[0], b)
+        assert np.all(np.triu(Y[:r], 1) == 0.0) and np.all(np.diag(Y[:r]) == 1.0)
+    Q = q_from_panels(Aout, T, n, b, p)
+    assert M.orthogonality(Q) <= 10
+    rec = np.linalg.norm(Q @ B @ Q.T - A) / (n * np.linalg.norm(A) * M.EPS)
+    assert rec <= 10
+
+
+def test_sbr_upper_matches_lower():
+    n, b = 200, 16
+    A = W.gaussian_sym(n, seed=4)
+    AB_l, _, _, _ = run_sbr(A, b, "L")
+    junk = np.triu(A) + np.tril(np.full_like(A, 7e7), -1)  # lower triangle garbage
+    AB_u, _, _, _ = run_sbr(junk, b, "U")
+    assert np.array_equal(AB_l, AB_u)
+
+
+def test_sbr_known_spectrum():
+    n, b = 400, 32
+    A, lam = W.known_spectrum(n, seed=2, spectrum="clustered", reflectors=16)
+    AB, _, _, _ = run_sbr(A, b)
+    B = band_to_dense(AB, n, b, 2 * b + 1)
+    assert M.eig_error(np.linalg.eigvalsh(B), lam) <= 1e-13
