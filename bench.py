@@ -1,0 +1,182 @@
+"""Benchmark: plain FP64 dense symmetric EVD with eigenvectors on one MI355X.
+
+One step = one full evd_dsyevd call (SBR, BC, D&C, SBR-back, BC-back, final
+GEMM) on an n x n matrix that is already resident in HBM; the matrix is
+restored from a device copy before each call (the copy is inside the timed
+region and costs well under 1% of a step).
+
+Workload: n = 32768, A = (G + G^T) / (2 sqrt(n)), G iid N(0, 1) drawn on the
+GPU from torch's Philox generator seeded with 3; band width b = 64.
+Metric: EVD TFLOPS at the 4n^3/3 convention (T3 = (4n^3/3)/t), plus time to
+solution; T1 = 4n^3/t (the paper's convention) is reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--b B]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (MFMA and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n: int = 2048):
+    """The CPU oracle (one-stage Householder + implicit QL, with vectors) on a
+    bounded sample of the same workload: one n x n matrix of the same recipe."""
+    import numpy as np
+    import oracle
+    from paper_2511_16174_amd import workloads
+
+    A = workloads.gaussian_sym(n, seed=3, scaled=True)
+    t0 = time.perf_counter()
+    oracle.syev(A, jobz="V")
+    t = time.perf_counter() - t0
+    return {
+        "value": (4.0 * n ** 3 / 3.0) / t / 1e12,
+        "unit": "TFLOPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"one n={n} matrix of the same recipe, eigenvalues+vectors, {t:.2f} s",
+        "seconds": t,
+        "n": n,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--b", type=int, default=64)
+    ap.add_argument("--jobz", default="V")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2511_16174_amd import evd
+
+    n, b = args.n, args.b
+    dev = torch.device("cuda:0")
+    ctx = evd.context(0)
+    ctx.set_param("b", b)
+    ctx.set_param("timing", 1)
+
+    log(f"[bench] generating n={n} on the GPU")
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    G = torch.randn((n, n), dtype=torch.float64, device=dev, generator=g)
+    A0 = (G + G.t()) * (0.5 / n ** 0.5)   # symmetric: row-major == column-major
+    del G
+    A = torch.empty_like(A0)
+    W = torch.empty(n, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    wb = ctx.evd_dsyevd_work_size(args.jobz, "L", n, n)
+    work = torch.empty(wb // 8 + 64, dtype=torch.float64, device=dev)
+    log(f"[bench] workspace {wb / 2**30:.1f} GiB")
+
+    def step():
+        A.copy_(A0)
+        ctx.evd_dsyevd(args.jobz, "L", n, A, n, W, work, wb, info)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i} stages(ms)={['%.1f' % x for x in ctx.stage_times()]}")
+    stage_sum = [0.0] * 8
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        st = ctx.stage_times()   # the timing mode synchronises on the last stage
+        stage_sum = [a + b_ for a, b_ in zip(stage_sum, st)]
+        log(f"[bench] step {i} stages(ms)={['%.1f' % x for x in st]}")
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    assert int(info.item()) == 0, "tridiagonal solver did not converge"
+    stage_ms = [x / args.steps for x in stage_sum]
+
+    flops3 = 4.0 * n ** 3 / 3.0
+    value = flops3 / t / 1e12
+    names = ["sbr", "bc", "dc", "sbr_back", "bc_back", "final_gemm", "total"]
+    stages = {names[i]: round(stage_ms[i], 3) for i in range(7)}
+
+    # roofline of the dominant single-launch kernel, timed live by the
+    # per-stage events on the library's stream: BC-back (one launch, 2 n^3
+    # FP64 flops) or the final GEMM (one launch, 2 n^3 flops)
+    if args.jobz.upper() == "V":
+        cand = {"bc_back": stage_ms[4], "final_gemm": stage_ms[5]}
+        kname = max(cand, key=cand.get)
+        kms = cand[kname]
+        achieved = 2.0 * n ** 3 / (kms * 1e-3) / 1e12
+        roofline = {"kernel": "bcback_kernel" if kname == "bc_back" else "gemm_f64_kernel (final Q_sb Q_d)",
+                    "bound": "alu" if kname == "bc_back" else "mfma",
+                    "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                    "algorithmic_flops_per_launch": 2.0 * n ** 3, "launch_ms": round(kms, 3)}
+    else:
+        roofline = None
+
+    out = {
+        "metric": "EVD TFLOPS (4n^3/3) and time-to-solution, plain FP64 with eigenvectors",
+        "value": round(value, 4),
+        "unit": "TFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t * 1e3, 2),
+        "time_to_solution_s": round(t, 4),
+        "tflops_4n3": round(4.0 * n ** 3 / t / 1e12, 4),
+        "frac_fp64_peak": round(value / PEAK_FP64_TFLOPS, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plain FP64 EVD with eigenvectors, n={n}, A=(G+G^T)/(2 sqrt n), G iid N(0,1)",
+                   "n": n, "b": b, "jobz": args.jobz, "uplo": "L", "seed": 3},
+        "stage_ms": stages,
+        "roofline": roofline,
+    }
+
+    if not args.no_verify and args.jobz.upper() == "V":
+        # independent check of the timed result (not timed): FP64 GEMMs from torch
+        Q = A.t()  # column-major eigenvectors -> Q[i, j] view
+        eps = 2.0 ** -52
+        with torch.no_grad():
+            R = A0 @ Q - Q * W[None, :]
+            res = (torch.linalg.norm(R) / (n * torch.linalg.norm(A0) * eps)).item()
+            del R
+            O = Q.t() @ Q
+            O.diagonal().sub_(1.0)
+            orth = (torch.linalg.norm(O) / (n * eps)).item()
+            del O
+            tr = abs(W.sum().item() - torch.trace(A0).item())
+        out["accuracy"] = {"rho_res": round(res, 3), "rho_orth": round(orth, 3), "trace_err": tr}
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -217,7 +217,7 @@ evd_status_t bc_run(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, 
         hipLaunchKernelGGL(bc_fill_int, dim3((unsigned)(evd_ceil_div(n, 256) < 1024 ? evd_ceil_div(n, 256) : 1024)),
                            dim3(256), 0, s, prog, n, 0);
         if (store_v) {
-            const int64_t steps = evd_bc_num_steps(n, b);
+            const int64_t steps = bc_num_steps(n, b);
             const int64_t nv = steps * n * b, nt = steps * n;
             hipLaunchKernelGGL(bc_zero_v_kernel, dim3(4096), dim3(256), 0, s, V, TAU, nv, nt);
         }
@@ -241,11 +241,7 @@ evd_status_t bc_run(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, 
 
 extern "C" {
 
-int64_t evd_bc_num_steps(int64_t n, int64_t b)
-{
-    if (b <= 0 || n < 3) return 0;
-    return (n - 2) / b + 1;  // steps of sweep 0: s with 1 + s b <= n - 1
-}
+int64_t evd_bc_num_steps(int64_t n, int64_t b) { return bc_num_steps(n, b); }
 
 evd_status_t evd_dsb2st_work_size(evd_ctx_t ctx, int64_t n, size_t *bytes)
 {

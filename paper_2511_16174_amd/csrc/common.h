@@ -101,4 +101,6 @@ struct GemmProblem {
     int64_t m, n, k;
 };
 evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob, int64_t max_m, int64_t max_n);
-extern "C" int64_t evd_bc_num_steps(int64_t n, int64_t b);
+// Steps of bulge-chasing sweep 0 (the longest): s >= 0 with 1 + s b <= n - 1.
+extern "C" int64_t evd_sbr_num_panels(int64_t n, int64_t b);
+__host__ __device__ inline int64_t bc_num_steps(int64_t n, int64_t b) { return (b <= 0 || n < 3) ? 0 : (n - 2) / b + 1; }

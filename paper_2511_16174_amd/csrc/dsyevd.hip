@@ -1,0 +1,174 @@
+// dsyevd-style driver: the two-stage pipeline of the paper in the reordered
+// stage order of Section 3.3.
+//
+//   SBR (A -> band B, panel reflectors)      stage 1   (Section 2.1.1, Eq. 1)
+//   BC  (B -> T = tridiag(e, d, e), U)       stage 2   (Section 2.1.1)
+//   D&C (T -> Lambda, Q_d)                   stage 3   (independent of 4a/4b)
+//   SBR-back (Q_s on the identity)           stage 4a  (Section 2.1.2)
+//   BC-back  (Q_sb = Q_s H_1 ... H_m)        stage 4b  (Section 4.3)
+//   final GEMM Q = Q_sb Q_d                  stage 5   (Section 3.3)
+// Eigenvalues only: SBR -> BC (no reflectors kept) -> bisection.
+#include "common.h"
+
+evd_status_t sbr_run(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda, double *AB,
+                     int64_t ldab, double *T, void *work);
+size_t sbr_work_bytes(int64_t n, int64_t b);
+evd_status_t bc_run(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, int64_t ldab, double *d, double *e,
+                    double *V, double *TAU, int *prog);
+size_t dc_work_bytes(char compz, int64_t n);
+evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const double *e, double *W, double *Z,
+                    int64_t ldz, void *work, int32_t *info);
+evd_status_t orgsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *Q,
+                       int64_t ldq, void *work);
+size_t orgsb_work_bytes(int64_t n, int64_t b);
+evd_status_t bcback_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
+                        double *Q, int64_t ldq);
+
+namespace {
+
+int64_t choose_b(evd_ctx_t ctx, int64_t n)
+{
+    int64_t b = ctx->b;
+    if (b <= 0) b = (n <= 4096) ? 32 : 64;
+    // the band must be narrower than the matrix for SBR to have work; a band
+    // as wide as the matrix is handled by BC directly
+    while (b > 1 && b >= n) b >>= 1;
+    if (b < 1) b = 1;
+    return b;
+}
+
+struct EvdWork {
+    double *AB, *T, *d, *e, *V, *TAU, *Qs, *Qd;
+    int *prog;
+    void *sbr, *dc, *orgsb;
+    int64_t b, ldab;
+};
+
+size_t evd_layout(int64_t n, int64_t b, bool vec, char *base, EvdWork *w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += evd_align256(bytes > 0 ? bytes : 1);
+        return (void *)p;
+    };
+    EvdWork t;
+    t.b = b;
+    t.ldab = 2 * b + 1;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const int64_t p = evd_sbr_num_panels(n, b);
+    const int64_t steps = bc_num_steps(n, b);
+    t.AB = (double *)take((size_t)t.ldab * nn * 8);
+    t.T = (double *)take((size_t)(p > 0 ? p : 1) * b * b * 8);
+    t.d = (double *)take(nn * 8);
+    t.e = (double *)take(nn * 8);
+    t.prog = (int *)take(nn * 4);
+    t.sbr = take(sbr_work_bytes(n, b));
+    if (vec) {
+        t.V = (double *)take((size_t)(steps > 0 ? steps : 1) * nn * b * 8);
+        t.TAU = (double *)take((size_t)(steps > 0 ? steps : 1) * nn * 8);
+        t.Qs = (double *)take(nn * nn * 8);
+        t.Qd = (double *)take(nn * nn * 8);
+        t.dc = take(dc_work_bytes('I', n));
+        t.orgsb = take(orgsb_work_bytes(n, b));
+    } else {
+        t.V = t.TAU = t.Qs = t.Qd = nullptr;
+        t.dc = take(dc_work_bytes('N', n));
+        t.orgsb = nullptr;
+    }
+    if (w) *w = t;
+    return off;
+}
+
+__global__ void trivial_kernel(int64_t n, double *A, double *W, int vec, int32_t *info)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (n == 1) {
+            W[0] = A[0];
+            if (vec) A[0] = 1.0;
+        }
+        if (info) info[0] = 0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+evd_status_t evd_dsyevd_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n, int64_t lda, size_t *bytes)
+{
+    if (!ctx || !bytes) return EVD_ERR_INVALID_ARG;
+    const bool vec = (jobz == 'V' || jobz == 'v');
+    int bad = 0;
+    if (!(vec || jobz == 'N' || jobz == 'n')) bad = 2;
+    else if (!(uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u')) bad = 3;
+    else if (n < 0) bad = 4;
+    else if (lda < (n > 1 ? n : 1)) bad = 5;
+    ctx->last_invalid_arg = bad;
+    if (bad) return EVD_ERR_INVALID_ARG;
+    *bytes = evd_layout(n, choose_b(ctx, n), vec, nullptr, nullptr);
+    return EVD_OK;
+}
+
+evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda, double *W, void *work,
+                        size_t work_bytes, int32_t *info)
+{
+    if (!ctx) return EVD_ERR_INVALID_ARG;
+    const bool vec = (jobz == 'V' || jobz == 'v');
+    const int64_t b = choose_b(ctx, n);
+    int bad = 0;
+    if (!(vec || jobz == 'N' || jobz == 'n')) bad = 2;
+    else if (!(uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u')) bad = 3;
+    else if (n < 0) bad = 4;
+    else if (n > 0 && !A) bad = 5;
+    else if (lda < (n > 1 ? n : 1)) bad = 6;
+    else if (n > 0 && !W) bad = 7;
+    else if (n > 0 && !work) bad = 8;
+    else if (work_bytes < evd_layout(n, b, vec, nullptr, nullptr)) bad = 9;
+    ctx->last_invalid_arg = bad;
+    if (bad) return bad == 9 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
+    if (n == 0) return EVD_OK;
+    if (ctx->device < 0) return EVD_ERR_HIP;
+    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    hipStream_t s = ctx->stream;
+    const bool timing = ctx->timing != 0;
+    for (int i = 0; i < 8; ++i) ctx->stage_ms[i] = 0.0f;
+    if (n == 1) {
+        hipLaunchKernelGGL(trivial_kernel, dim3(1), dim3(64), 0, s, n, A, W, vec ? 1 : 0, info);
+        return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    }
+    EvdWork w;
+    evd_layout(n, b, vec, (char *)work, &w);
+    auto mark = [&](int i) { if (timing) (void)hipEventRecord(ctx->ev[i], s); };
+
+    mark(0);
+    EVD_CHECK(sbr_run(ctx, uplo, n, b, A, lda, w.AB, w.ldab, w.T, w.sbr));
+    mark(1);
+    EVD_CHECK(bc_run(ctx, vec ? 'V' : 'N', n, b, w.AB, w.ldab, w.d, w.e, w.V, w.TAU, w.prog));
+    mark(2);
+    if (!vec) {
+        EVD_CHECK(dc_run(ctx, 'N', n, w.d, w.e, W, nullptr, 1, w.dc, info));
+        mark(3);
+    } else {
+        EVD_CHECK(dc_run(ctx, 'I', n, w.d, w.e, W, w.Qd, n, w.dc, info));
+        mark(3);
+        EVD_CHECK(orgsb_run(ctx, n, b, A, lda, w.T, w.Qs, n, w.orgsb));
+        mark(4);
+        EVD_CHECK(bcback_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n));
+        mark(5);
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, w.Qs, n, w.Qd, n, 0.0, A, lda, nullptr, 0));
+        mark(6);
+    }
+    if (timing) {
+        if (hipEventSynchronize(ctx->ev[vec ? 6 : 3]) != hipSuccess) return EVD_ERR_HIP;
+        float ms = 0.0f;
+        const int last = vec ? 6 : 3;
+        for (int i = 0; i < last; ++i) {
+            if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess) ctx->stage_ms[i] = ms;
+        }
+        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[last]) == hipSuccess) ctx->stage_ms[6] = ms;
+    }
+    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+"""End-to-end parity of the GPU eigendecomposition (evd_dsyevd through the C
+ABI) with the CPU oracle, closed forms and known spectra.
+
+Gates (per eigendecomposition, eps = 2^-52):
+  rho_res  = ||A Q - Q diag(w)||_F / (n ||A||_F eps) <= 10
+  rho_orth = ||Q^T Q - I||_F / (n eps)              <= 10
+  eta      = max |w - w_ref| / ||A||_2              <= 1e-12
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.metrics as M
+from paper_2511_16174_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RES, ORTH, ETA = 10.0, 10.0, 1e-12
+
+
+def gpu_eigh(A, jobz="V", uplo="L", b=0):
+    from paper_2511_16174_amd import evd
+    import torch
+    At = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    out = evd.eigh(At, jobz=jobz, uplo=uplo, b=b)
+    torch.cuda.synchronize()
+    if jobz == "V":
+        w, Q = out
+        return w.cpu().numpy(), Q.cpu().numpy()
+    return out.cpu().numpy(), None
+
+
+def check(A, w, Q, w_ref):
+    assert np.all(np.diff(w) >= 0), "eigenvalues must be ascending"
+    eta = M.eig_error(w, w_ref)
+    assert eta <= ETA, eta
+    if Q is not None:
+        res, orth = M.residual(A, w, Q), M.orthogonality(Q)
+        assert res <= RES, res
+        assert orth <= ORTH, orth
+
+
+def test_config_n512_b32_vs_oracle():
+    """Plain FP64 EVD with vectors, n = 512, A = (G + G^T)/2, b = 32."""
+    A = W.gaussian_sym(512, seed=1)
+    w, Q = gpu_eigh(A, b=32)
+    w_ref, Q_ref = oracle.syev(A)
+    check(A, w, Q, w_ref)
+    # eigenvectors of well separated eigenvalues agree up to sign (Davis-Kahan)
+    gaps = np.minimum(np.r_[np.inf, np.diff(w_ref)], np.r_[np.diff(w_ref), np.inf])
+    norm2 = max(abs(w_ref[0]), abs(w_ref[-1]))
+    for c in np.where(gaps >= 1e-6 * norm2)[0]:
+        s = np.sign(Q[:, c] @ Q_ref[:, c])
+        assert np.linalg.norm(Q[:, c] - s * Q_ref[:, c]) <= 100 * np.sqrt(512) * M.EPS * norm2 / gaps[c]
+
+
+@pytest.mark.parametrize("n,b", [(2, 0), (3, 0), (5, 4), (31, 8), (33, 16), (63, 32), (64, 32), (65, 64),
+                                 (100, 4), (129, 64), (257, 16), (300, 2), (700, 64)])
+def test_sizes_and_bands(n, b):
+    A = W.gaussian_sym(n, seed=10 + n)
+    w, Q = gpu_eigh(A, b=b)
+    check(A, w, Q, oracle.syev(A, jobz="N"))
+
+
+def test_n1():
+    A = np.array([[-2.5]])
+    w, Q = gpu_eigh(A)
+    assert w[0] == -2.5 and Q[0, 0] == 1.0
+
+
+@pytest.mark.parametrize("n", [100, 512])
+def test_values_only(n):
+    A = W.gaussian_sym(n, seed=3)
+    w, _ = gpu_eigh(A, jobz="N")
+    check(A, w, None, oracle.syev(A, jobz="N"))
+
+
+def test_uplo_upper():
+    A = W.gaussian_sym(200, seed=8)
+    junk = np.triu(A) + np.tril(np.full_like(A, 3e7), -1)
+    w, Q = gpu_eigh(junk, uplo="U", b=16)
+    check(A, w, Q, oracle.syev(A, jobz="N"))
+
+
+@pytest.mark.parametrize("spectrum", ["clustered", "logspaced", "geometric", "cluster0", "cluster1"])
+def test_known_spectra(spectrum):
+    n = 600
+    A, lam = W.known_spectrum(n, seed=4, spectrum=spectrum, reflectors=16)
+    w, Q = gpu_eigh(A, b=32)
+    check(A, w, Q, lam)
+
+
+@pytest.mark.parametrize("L", [6, 8, 11])
+def test_clean_torus_degenerate(L):
+    A = W.tight_binding(L)
+    w, Q = gpu_eigh(A, b=16)
+    check(A, w, Q, W.tight_binding_clean_eigenvalues(L))
+
+
+def test_rotated_laplacian_closed_form():
+    n = 400
+    A = W.apply_reflectors_two_sided(W.laplacian_1d(n), W.reflector_vectors(n, 8, W.rng(12)))
+    w, Q = gpu_eigh(A, b=32)
+    check(A, w, Q, W.laplacian_eigenvalues(n))
+
+
+def test_trace_frobenius_invariants():
+    A = W.gaussian_sym(800, seed=21, scaled=True)
+    w, _ = gpu_eigh(A, jobz="N")
+    assert abs(w.sum() - np.trace(A)) <= 1e-12 * 800
+    assert abs((w ** 2).sum() - (A ** 2).sum()) <= 1e-12 * (A ** 2).sum()
