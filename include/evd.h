@@ -66,6 +66,8 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "bc_waves"     number of persistent bulge-chasing wavefronts, 0 = automatic
  *   "order"        0 = reordered stages (paper Section 3.3), 1 = conventional order
  *   "timing"       1 = record per-stage times (host-synchronising; for benchmarks)
+ *   "panel_wgs"    cap on the workgroups of one panel-QR launch, 0 = automatic
+ *   "batch_streams", "batch_graph", "last_graph_used"  see evd_dsyevd_batched
  * Unknown keys return EVD_ERR_INVALID_ARG. */
 evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value);
 evd_status_t evd_get_param(evd_ctx_t ctx, const char *key, int64_t *value /*[host]*/);
@@ -96,6 +98,17 @@ evd_status_t evd_dgemm(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_t m
                        double beta, double *C, int64_t ldc, void *work, size_t work_bytes);
 evd_status_t evd_dgemm_work_size(evd_ctx_t ctx, int64_t m, int64_t n, int64_t k, size_t *bytes /*[host]*/);
 
+/* FP32 GEMM through split-BF16x3 on matrix cores (mixed-precision path; not
+ * in the paper): each FP32 operand is split into bf16 hi + lo parts and
+ * C = alpha (A_hi B_hi + A_hi B_lo + A_lo B_hi) + beta C with FP32
+ * accumulation; about 17 significant bits per product (relative error of a
+ * dot product ~ 3 * 2^-17 + FP32 accumulation).  Same op conventions as
+ * evd_dgemm ('S' only with opb 'N'; lower_c not with 'S'). */
+evd_status_t evd_sgemm_x3(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_t m, int64_t n, int64_t k,
+                          float alpha, const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
+                          float *C, int64_t ldc, void *work, size_t work_bytes);
+evd_status_t evd_sgemm_x3_work_size(evd_ctx_t ctx, int64_t m, int64_t n, int64_t k, size_t *bytes /*[host]*/);
+
 /* ------------------------------------------------------------------ full EVD */
 
 /* dsyevd-style driver (LAPACK convention; paper Section 1).
@@ -110,6 +123,60 @@ evd_status_t evd_dsyevd_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n
                                   size_t *bytes /*[host]*/);
 evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda,
                         double *W, void *work, size_t work_bytes, int32_t *info);
+
+/* Mixed-precision EVD with FP64 refinement (an extension beside the paper's
+ * FP64 path; not in the paper).  The pipeline of evd_dsyevd runs in FP32
+ * (panel QR, bulge chasing and BC-back on FP32 vector units; every product
+ * through split-BF16x3 matrix cores, see evd_sgemm_x3), the tridiagonal
+ * eigenproblem in FP64, then `sweeps` FP64 Ogita-Aishima refinement sweeps
+ * (R = I - X^T X, S = X^T A X, lam_i = s_ii/(1 - r_ii),
+ * E_ij = (s_ij + lam_j r_ij)/(lam_j - lam_i) if |lam_i - lam_j| > delta else
+ * r_ij/2, X <- X + X E) improve the eigenpairs.  Outputs as evd_dsyevd
+ * (jobz must be 'V'; W ascending, eigenvectors in A; W holds the Rayleigh
+ * quotients of the returned vectors).  0 <= sweeps <= 8.
+ * stats (optional, device, 8 doubles): [0] delta of the last sweep,
+ * [1] ||S - diag(lam)||_F, [2] ||R||_F, [3] max |lam|, [4] the FP64 residual
+ * ||A X - X diag(W)||_F / (n ||A||_F) of the returned pairs.
+ * Stage times ("timing" = 1): [0] SBR, [1] BC, [2] D&C, [3] SBR-back,
+ * [4] BC-back, [5] final product, [6] refinement, [7] total. */
+evd_status_t evd_dsyevd_mixed_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n, int64_t lda,
+                                        size_t *bytes /*[host]*/);
+evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda,
+                              double *W, int32_t sweeps, void *work, size_t work_bytes, int32_t *info,
+                              double *stats);
+
+/* Autotuner for the band half-width b (the paper fixes b = 32 for its
+ * platform, Section 4.1; the best b depends on the GPU and on n).  Times
+ * evd_dsyevd on A (n x n, lower triangle, not modified) for b in
+ * {16, 32, 64} (two calls each, the second timed with events on the stream;
+ * this call synchronises) and records the fastest b for n's size bucket
+ * floor(log2 n) in the context, where evd_dsyevd, evd_dsyevd_mixed and the
+ * work-size queries use it while the "b" parameter is 0.
+ * [host] best_b, best_ms may be NULL. */
+evd_status_t evd_autotune_work_size(evd_ctx_t ctx, char jobz, int64_t n, size_t *bytes /*[host]*/);
+evd_status_t evd_autotune(evd_ctx_t ctx, char jobz, int64_t n, const double *A, int64_t lda, void *work,
+                          size_t work_bytes, int64_t *best_b, float *best_ms);
+
+/* Batched EVD of many uneven-size matrices (an extension beside the paper's
+ * method; tight-binding models are one of its applications, Section 1).
+ * Matrix i (n[i] x n[i], leading dimension lda[i]) is solved exactly as by
+ * evd_dsyevd: eigenvalues into W[i], eigenvectors into A[i] (jobz 'V').
+ * n, lda: [host] arrays of `batch` sizes.  A, W: [host] arrays of `batch`
+ * DEVICE pointers.  info: device int32[batch] (per-matrix status).
+ * t_start_end (optional): device uint64[2*batch], wall_clock64 (100 MHz) ticks
+ * at the start and end of every matrix.
+ * Matrices are ordered by decreasing n^3 and spread over "batch_streams"
+ * (default 4) streams; the launch sequence is captured once into a hipGraph
+ * ("batch_graph" = 1, default) and replayed while sizes and pointers are
+ * unchanged ("last_graph_used" reports whether the graph ran).  Persistent
+ * kernels are capped at (compute units / streams) workgroups each.
+ * work: evd_dsyevd_batched_work_size() bytes. */
+evd_status_t evd_dsyevd_batched_work_size(evd_ctx_t ctx, char jobz, int32_t batch, const int64_t *n /*[host]*/,
+                                          const int64_t *lda /*[host]*/, size_t *bytes /*[host]*/);
+evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t batch, const int64_t *n /*[host]*/,
+                                double *const *A /*[host] array of device pointers*/,
+                                const int64_t *lda /*[host]*/, double *const *W /*[host] array of device pointers*/,
+                                void *work, size_t work_bytes, int32_t *info, uint64_t *t_start_end);
 
 /* ------------------------------------------------------------------ stages */
 

@@ -39,6 +39,7 @@ evd_status_t evd_create(evd_ctx_t *ctx, int device)
     memset(c, 0, sizeof(*c));
     c->device = device;
     c->stream = nullptr;
+    c->batch_graph = 1;
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) { delete c; return EVD_ERR_HIP; }
     if (hipSetDevice(device) != hipSuccess) { delete c; return EVD_ERR_HIP; }
@@ -58,6 +59,10 @@ evd_status_t evd_destroy(evd_ctx_t ctx)
     if (!ctx) return EVD_ERR_INVALID_ARG;
     for (int i = 0; i < 16; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (int i = 0; i < ctx->nbstreams; ++i) (void)hipStreamDestroy(ctx->bstreams[i]);
+    for (int i = 0; i < 17; ++i)
+        if (ctx->bev[i]) (void)hipEventDestroy(ctx->bev[i]);
     delete ctx;
     return EVD_OK;
 }
@@ -77,6 +82,10 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "bcback_group")) return &ctx->bcback_group;
     if (!strcmp(key, "order")) return &ctx->order;
     if (!strcmp(key, "timing")) return &ctx->timing;
+    if (!strcmp(key, "panel_wgs")) return &ctx->panel_wgs;
+    if (!strcmp(key, "batch_streams")) return &ctx->batch_streams;
+    if (!strcmp(key, "batch_graph")) return &ctx->batch_graph;
+    if (!strcmp(key, "last_graph_used")) return &ctx->last_graph_used;
     return nullptr;
 }
 

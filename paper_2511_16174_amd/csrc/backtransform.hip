@@ -14,38 +14,37 @@
 // columns that slides left by b columns when s decreases, so each row keeps the
 // window in registers and streams only b columns in and out per G reflectors.
 //
-// Register layout: a row of Q is spread over 4 lanes (lane = row + 16 rho);
-// lane rho holds window columns 4k + rho, k = 0 .. NW-1.  Reflector jj of the
-// group touches window columns jj .. jj+b-1, i.e. slots k = jj/4 .. jj/4 + b/4
-// on every lane (out-of-range entries meet zero padding of v).  The four
-// partial dot products of a row are combined with two cross-lane shuffles.
+// Register layout: a row of Q is spread over 4 adjacent lanes (lane =
+// 4 row + rho); lane rho holds window columns 4k + rho, k = 0 .. NW-1.
+// Reflector jj of the group touches window columns jj .. jj+b-1, i.e. slots
+// k = jj/4 .. jj/4 + b/4 on every lane (out-of-range entries meet zero padding
+// of v).  The four partial dot products of a row are combined with two DPP
+// quad permutations; each partial uses two accumulators to halve the FMA chain.
 #include "common.h"
 
 namespace {
 
-constexpr int BCB_ROWS = 128;                 // rows of Q per workgroup
-constexpr int BCB_THREADS = BCB_ROWS * 4;     // 4 lanes per row
 constexpr int BCB_G = 64;                     // sweeps per block
 constexpr int VPAD = 4;                       // zero padding on each side of v
 
-template <int B>
-__global__ __launch_bounds__(BCB_THREADS) void bcback_kernel(int64_t mrows, int64_t n, const double *__restrict__ V,
-                                                             const double *__restrict__ TAU, double *__restrict__ Q,
+template <int B, typename T, int ROWS>
+__global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t n, const T *__restrict__ V,
+                                                             const T *__restrict__ TAU, T *__restrict__ Q,
                                                              int64_t ldq)
 {
     constexpr int G = BCB_G;
+    constexpr int BCB_THREADS = ROWS * 4;
     constexpr int NW = (G + B) / 4;       // slots per lane (window G+B-1 columns, one spare)
     constexpr int SH = B / 4;             // slots shifted per step
     constexpr int LDV = B + 2 * VPAD;
-    __shared__ double vs[2][G][LDV];
-    __shared__ double ts[2][G];
+    __shared__ T vs[2][G][LDV];
+    __shared__ T ts[2][G];
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int rho = lane >> 4;                            // residue of this lane
-    const int64_t row = (int64_t)blockIdx.x * BCB_ROWS + wave * 16 + (lane & 15);
+    const int rho = tid & 3;                              // residue of this lane
+    const int64_t row = (int64_t)blockIdx.x * ROWS + (tid >> 2);
     const bool rowok = row < mrows;
-    double *Qr = Q + row;
+    T *Qr = Q + row;
 
     const int64_t nsweeps = n - 2;
     const int64_t nsteps = bc_num_steps(n, B);
@@ -66,8 +65,8 @@ __global__ __launch_bounds__(BCB_THREADS) void bcback_kernel(int64_t mrows, int6
         }
     };
 
-    double x[NW];
-    double pre[SH];
+    T x[NW];
+    T pre[SH];
     for (int64_t c0 = 0; c0 < nsweeps; c0 += G) {
         // steps of the first sweep of the block bound the block's steps
         const int64_t rem = n - 1 - (c0 + 1);
@@ -98,19 +97,18 @@ __global__ __launch_bounds__(BCB_THREADS) void bcback_kernel(int64_t mrows, int6
             // apply the G reflectors of step s, sweeps ascending
 #pragma unroll
             for (int jj = 0; jj < G; ++jj) {
-                const double tau = ts[buf][jj];
-                const double *v = &vs[buf][jj][VPAD + rho - jj];
+                const T tau = ts[buf][jj];
+                const T *v = &vs[buf][jj][VPAD + rho - jj];
                 constexpr int CNT = B / 4 + 1;
                 const int k0 = jj / 4;
-                double dot = 0.0;
+                T d0 = 0.0, d1 = 0.0;
 #pragma unroll
-                for (int q = 0; q < CNT; ++q) {
+                for (int q = 0; q < CNT; q += 2) {
                     const int k = k0 + q;
-                    if (k < NW) dot += x[k] * v[4 * k];
+                    if (k < NW) d0 += x[k] * v[4 * k];
+                    if (q + 1 < CNT && k + 1 < NW) d1 += x[k + 1] * v[4 * (k + 1)];
                 }
-                dot += __shfl_xor(dot, 16, 64);
-                dot += __shfl_xor(dot, 32, 64);
-                const double w = tau * dot;
+                const T w = tau * quad_sum(d0 + d1);
 #pragma unroll
                 for (int q = 0; q < CNT; ++q) {
                     const int k = k0 + q;
@@ -144,22 +142,23 @@ __global__ __launch_bounds__(BCB_THREADS) void bcback_kernel(int64_t mrows, int6
 
 // Plain version for b < 4 (and any b): one thread per row, reflectors in
 // generation order, Q read and written in global memory.
-__global__ void bcback_simple_kernel(int64_t mrows, int64_t n, int64_t b, const double *__restrict__ V,
-                                     const double *__restrict__ TAU, double *__restrict__ Q, int64_t ldq)
+template <typename T>
+__global__ void bcback_simple_kernel(int64_t mrows, int64_t n, int64_t b, const T *__restrict__ V,
+                                     const T *__restrict__ TAU, T *__restrict__ Q, int64_t ldq)
 {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= mrows) return;
     const int64_t nsteps = bc_num_steps(n, b);
-    double *Qr = Q + row;
+    T *Qr = Q + row;
     for (int64_t c = 0; c + 2 < n; ++c) {
         for (int64_t s = 0; s < nsteps; ++s) {
             const int64_t r = c + 1 + s * b;
             if (r >= n) break;
-            const double tau = TAU[s * n + c];
+            const T tau = TAU[s * n + c];
             if (tau == 0.0) continue;
             const int64_t m = (n - r) < b ? (n - r) : b;
-            const double *v = V + (s * n + c) * b;
-            double dot = 0.0;
+            const T *v = V + (s * n + c) * b;
+            T dot = 0.0;
             for (int64_t i = 0; i < m; ++i) dot += Qr[(r + i) * ldq] * v[i];
             dot *= tau;
             for (int64_t i = 0; i < m; ++i) Qr[(r + i) * ldq] -= dot * v[i];
@@ -167,7 +166,8 @@ __global__ void bcback_simple_kernel(int64_t mrows, int64_t n, int64_t b, const 
     }
 }
 
-__global__ void eye_kernel(int64_t n, double *Q, int64_t ldq)
+template <typename T>
+__global__ void eye_kernel(int64_t n, T *Q, int64_t ldq)
 {
     const int64_t total = n * n;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -178,48 +178,90 @@ __global__ void eye_kernel(int64_t n, double *Q, int64_t ldq)
 
 }  // namespace
 
-evd_status_t bcback_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
-                        double *Q, int64_t ldq)
+namespace {
+template <typename T>
+evd_status_t bcback_run_t(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const T *V, const T *TAU, T *Q,
+                          int64_t ldq)
 {
     hipStream_t s = ctx->stream;
     if (n < 3 || mrows <= 0) return EVD_OK;
-    const dim3 grid((unsigned)evd_ceil_div(mrows, BCB_ROWS));
+    // 128-row blocks (8 wavefronts, up to 3 per SIMD) once there are enough
+    // rows for every compute unit to get half a block's worth; smaller blocks
+    // for small matrices (each block re-reads every reflector group)
+    const int rows = (mrows >= (int64_t)64 * ctx->num_cus) ? 128 : (mrows >= (int64_t)32 * ctx->num_cus ? 64 : 32);
+    const dim3 grid((unsigned)evd_ceil_div(mrows, rows));
+    const dim3 blk(rows * 4);
+#define EVD_BCB(BB)                                                                                          \
+    if (rows == 128) hipLaunchKernelGGL((bcback_kernel<BB, T, 128>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq); \
+    else if (rows == 64) hipLaunchKernelGGL((bcback_kernel<BB, T, 64>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq); \
+    else hipLaunchKernelGGL((bcback_kernel<BB, T, 32>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq);
     switch (b) {
-    case 4: hipLaunchKernelGGL(bcback_kernel<4>, grid, dim3(BCB_THREADS), 0, s, mrows, n, V, TAU, Q, ldq); break;
-    case 8: hipLaunchKernelGGL(bcback_kernel<8>, grid, dim3(BCB_THREADS), 0, s, mrows, n, V, TAU, Q, ldq); break;
-    case 16: hipLaunchKernelGGL(bcback_kernel<16>, grid, dim3(BCB_THREADS), 0, s, mrows, n, V, TAU, Q, ldq); break;
-    case 32: hipLaunchKernelGGL(bcback_kernel<32>, grid, dim3(BCB_THREADS), 0, s, mrows, n, V, TAU, Q, ldq); break;
-    case 64: hipLaunchKernelGGL(bcback_kernel<64>, grid, dim3(BCB_THREADS), 0, s, mrows, n, V, TAU, Q, ldq); break;
+    case 4: EVD_BCB(4) break;
+    case 8: EVD_BCB(8) break;
+    case 16: EVD_BCB(16) break;
+    case 32: EVD_BCB(32) break;
+    case 64: EVD_BCB(64) break;
     default:
-        hipLaunchKernelGGL(bcback_simple_kernel, dim3((unsigned)evd_ceil_div(mrows, 256)), dim3(256), 0, s, mrows, n,
+        hipLaunchKernelGGL(bcback_simple_kernel<T>, dim3((unsigned)evd_ceil_div(mrows, 256)), dim3(256), 0, s, mrows, n,
                            b, V, TAU, Q, ldq);
     }
+#undef EVD_BCB
     return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+}
+
+}  // namespace
+
+evd_status_t bcback_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
+                        double *Q, int64_t ldq)
+{
+    return bcback_run_t<double>(ctx, mrows, n, b, V, TAU, Q, ldq);
+}
+
+evd_status_t bcback_run_f32(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const float *V, const float *TAU,
+                            float *Q, int64_t ldq)
+{
+    return bcback_run_t<float>(ctx, mrows, n, b, V, TAU, Q, ldq);
 }
 
 size_t orgsb_work_bytes(int64_t n, int64_t b) { return evd_align256((size_t)2 * b * (n > 0 ? n : 1) * 8); }
 
 // Q_s = H^(0) H^(1) ... H^(p-1), H^(k) = I - Y_k T_k Y_k^T on rows/cols (k+1)b .. n-1,
 // accumulated backwards on the identity.
-evd_status_t orgsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *Q,
-                       int64_t ldq, void *work)
+namespace {
+template <typename T>
+evd_status_t orgsb_run_t(evd_ctx_t ctx, int64_t n, int64_t b, const T *A, int64_t lda, const T *Tf, T *Q,
+                         int64_t ldq, void *work)
 {
     hipStream_t s = ctx->stream;
-    hipLaunchKernelGGL(eye_kernel, dim3((unsigned)(evd_ceil_div(n * n, 256) < 8192 ? evd_ceil_div(n * n, 256) : 8192)),
+    hipLaunchKernelGGL(eye_kernel<T>, dim3((unsigned)(evd_ceil_div(n * n, 256) < 8192 ? evd_ceil_div(n * n, 256) : 8192)),
                        dim3(256), 0, s, n, Q, ldq);
-    double *W1 = (double *)work;
-    double *W2 = W1 + (size_t)b * n;
+    T *W1 = (T *)work;
+    T *W2 = W1 + (size_t)b * n;
     const int64_t p = evd_sbr_num_panels(n, b);
     for (int64_t k = p - 1; k >= 0; --k) {
         const int64_t j0 = k * b, i0 = j0 + b, m = n - i0;
-        const double *Y = A + i0 + j0 * lda;
-        double *Qs = Q + i0 + i0 * ldq;
+        const T *Y = A + i0 + j0 * lda;
+        T *Qs = Q + i0 + i0 * ldq;
         // W1 = Y^T Q_sub (b x m);  W2 = T W1;  Q_sub -= Y W2
-        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, b, m, m, 1.0, Y, lda, Qs, ldq, 0.0, W1, b, nullptr, 0));
-        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, b, m, b, 1.0, T + k * b * b, b, W1, b, 0.0, W2, b, nullptr, 0));
-        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, m, m, b, -1.0, Y, lda, W2, b, 1.0, Qs, ldq, nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, b, m, m, (T)1, Y, lda, Qs, ldq, (T)0, W1, b, (T *)nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, b, m, b, (T)1, Tf + k * b * b, b, W1, b, (T)0, W2, b, (T *)nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, m, b, (T)-1, Y, lda, W2, b, (T)1, Qs, ldq, (T *)nullptr, 0));
     }
     return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+}
+
+}  // namespace
+
+evd_status_t orgsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *Q,
+                       int64_t ldq, void *work)
+{
+    return orgsb_run_t<double>(ctx, n, b, A, lda, T, Q, ldq, work);
+}
+
+evd_status_t orgsb_run_f32(evd_ctx_t ctx, int64_t n, int64_t b, const float *A, int64_t lda, const float *T, float *Q,
+                           int64_t ldq, void *work)
+{
+    return orgsb_run_t<float>(ctx, n, b, A, lda, T, Q, ldq, work);
 }
 
 extern "C" {

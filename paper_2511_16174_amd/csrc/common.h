@@ -34,6 +34,12 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+__device__ __forceinline__ float wave_sum(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -41,17 +47,86 @@ __device__ __forceinline__ double wave_max(double v)
 }
 
 // Block-wide sum for blockDim.x a multiple of 64 (<= 1024).  `red` must hold
-// blockDim.x/64 doubles of LDS.  All threads get the result.
-__device__ __forceinline__ double block_sum(double v, double *red)
+// blockDim.x/64 values of LDS.  All threads get the result.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *red)
 {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();
     if (lane == 0) red[wid] = v;
     __syncthreads();
-    double s = 0.0;
+    T s = 0;
     for (int w = 0; w < nw; ++w) s += red[w];
     return s;
+}
+
+// Sum over the 4 lanes of each aligned quad (lanes 4q .. 4q+3) with DPP
+// quad permutations (no LDS round trip).
+__device__ __forceinline__ double quad_sum(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    double w = __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, true),
+                                __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, true));  // lane ^ 1
+    v += w;
+    lo = __double2loint(v);
+    hi = __double2hiint(v);
+    w = __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, true),
+                         __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, true));  // lane ^ 2
+    return v + w;
+}
+__device__ __forceinline__ float quad_sum(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+    return v;
+}
+
+// Device-coherent accesses for data shared between workgroups of one launch:
+// relaxed agent-scope atomics are emitted as sc1 loads/stores, which are
+// coherent across the chip's L2 caches without the whole-cache writeback and
+// invalidation that agent-scope release/acquire fences perform.  A producer
+// drains its own outstanding memory operations (mem_drain) before publishing
+// a flag with st_coh; a consumer issues its data loads only after it has
+// observed the flag with ld_coh.
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void mem_drain()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Grid-wide barrier for a co-resident (cooperative) launch of G workgroups:
+// bar[0] = arrival count (returns to 0), bar[1] = generation.  Data exchanged
+// across the barrier must be accessed with ld_coh / st_coh.
+__device__ __forceinline__ void grid_barrier_coh(int *bar, int G)
+{
+    mem_drain();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int g = ld_coh(&bar[1]);
+        mem_drain();
+        const int a = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == G - 1) {
+            st_coh(&bar[0], 0);
+            mem_drain();
+            st_coh(&bar[1], g + 1);
+        } else {
+            while (ld_coh(&bar[1]) == g) __builtin_amdgcn_s_sleep(1);
+        }
+        mem_drain();
+    }
+    __syncthreads();
 }
 
 // Agent-scope acquire / release on 32/64-bit flags in device memory.
@@ -83,7 +158,36 @@ struct evd_ctx_s {
     int max_coop_blocks_panel;
     hipEvent_t ev[16];
     float stage_ms[8];
+    // autotuned band width per size bucket (bucket = floor(log2 n)), 0 = none
+    int64_t tuned_b[64];
+    int64_t panel_wgs;        // cap on panel-QR workgroups (0 = automatic)
+    int64_t batch_streams;    // streams used by the batched driver (0 = 4)
+    int64_t batch_graph;      // 1 = capture the batched launch sequence in a hipGraph
+    int64_t last_graph_used;  // 1 if the last batched call ran from a graph
+    // batched driver state
+    hipStream_t bstreams[16];
+    hipEvent_t bev[17];
+    int nbstreams;
+    hipGraphExec_t gexec;
+    uint64_t gkey;
 };
+
+// Band width used by the drivers: explicit parameter, else the autotuned
+// value for n's size bucket, else the default (32 up to n = 4096, then 64),
+// halved until it is narrower than the matrix.
+inline int64_t evd_choose_b(const evd_ctx_s *ctx, int64_t n)
+{
+    int64_t b = ctx->b;
+    if (b <= 0 && n > 1) {
+        int bucket = 0;
+        while (bucket < 63 && ((int64_t)1 << (bucket + 1)) <= n) ++bucket;
+        b = ctx->tuned_b[bucket];
+    }
+    if (b <= 0) b = (n <= 4096) ? 32 : 64;
+    while (b > 1 && b >= n) b >>= 1;
+    if (b < 1) b = 1;
+    return b;
+}
 
 // ---------------------------------------------------------------- internal API
 // GEMM (gemm_f64.hip)
@@ -92,6 +196,14 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
                       double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
                       double beta, double *C, int64_t ldc, double *splitk_ws, size_t splitk_ws_elems);
 size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k);
+// Row (within a 16 x 16 tile) held by lane group lq = lane/16, element r, of
+// the FP32 accumulator of v_mfma_f32_16x16x32_bf16.
+#define EVD_F32_MFMA_ROW(lq, r) (4 * (lq) + (r))
+// FP32 split-BF16x3 GEMM (gemm_f32x3.hip)
+evd_status_t gemm_f32x3(hipStream_t s, int opa, int opb, int lower_c, int64_t m, int64_t n, int64_t k, float alpha,
+                        const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
+                        float *ws, size_t ws_elems);
+size_t gemm_f32x3_ws_elems(int64_t m, int64_t n, int64_t k);
 // Grouped C = A * B (no transposes) with per-problem sizes read on the device.
 struct GemmProblem {
     const double *A;
@@ -101,6 +213,25 @@ struct GemmProblem {
     int64_t m, n, k;
 };
 evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob, int64_t max_m, int64_t max_n);
+
+// Type-dispatched GEMM: FP64 MFMA for double, split-BF16x3 for float.
+inline evd_status_t gemm_t(hipStream_t s, int opa, int opb, int lower_c, int64_t m, int64_t n, int64_t k, double alpha,
+                           const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,
+                           int64_t ldc, double *ws, size_t ws_elems)
+{
+    return gemm_f64(s, opa, opb, lower_c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems);
+}
+inline evd_status_t gemm_t(hipStream_t s, int opa, int opb, int lower_c, int64_t m, int64_t n, int64_t k, float alpha,
+                           const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
+                           float *ws, size_t ws_elems)
+{
+    return gemm_f32x3(s, opa, opb, lower_c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems);
+}
+template <typename T>
+inline size_t gemm_ws_elems_t(int64_t m, int64_t n, int64_t k)
+{
+    return sizeof(T) == 8 ? gemm_splitk_ws_elems(m, n, k) : gemm_f32x3_ws_elems(m, n, k);
+}
 // Steps of bulge-chasing sweep 0 (the longest): s >= 0 with 1 + s b <= n - 1.
 extern "C" int64_t evd_sbr_num_panels(int64_t n, int64_t b);
 __host__ __device__ inline int64_t bc_num_steps(int64_t n, int64_t b) { return (b <= 0 || n < 3) ? 0 : (n - 2) / b + 1; }

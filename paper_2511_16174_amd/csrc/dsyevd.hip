@@ -26,16 +26,7 @@ evd_status_t bcback_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, cons
 
 namespace {
 
-int64_t choose_b(evd_ctx_t ctx, int64_t n)
-{
-    int64_t b = ctx->b;
-    if (b <= 0) b = (n <= 4096) ? 32 : 64;
-    // the band must be narrower than the matrix for SBR to have work; a band
-    // as wide as the matrix is handled by BC directly
-    while (b > 1 && b >= n) b >>= 1;
-    if (b < 1) b = 1;
-    return b;
-}
+int64_t choose_b(evd_ctx_t ctx, int64_t n) { return evd_choose_b(ctx, n); }
 
 struct EvdWork {
     double *AB, *T, *d, *e, *V, *TAU, *Qs, *Qd;

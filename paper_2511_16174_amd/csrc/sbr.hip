@@ -12,27 +12,26 @@
 // holding its rows in LDS for the whole factorization.  Column j needs two
 // chip-wide reductions (its norm, then v^T P for the remaining columns plus
 // Y^T v for the T factor); they are separated by grid barriers of a
-// cooperative launch.  The T factor (forward, column-wise:
+// cooperative launch (a counter/generation barrier on device-coherent
+// atomics; the partial sums crossing it use device-coherent accesses too).  The T factor (forward, column-wise:
 // T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T v_j)) is formed at the end by
 // workgroup 0 from the reduced Y^T v products.
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.h"
-
-namespace cg = cooperative_groups;
 
 namespace {
 
 constexpr int PANEL_THREADS = 256;
 
-__global__ void fill_kernel(double *p, int64_t count, double v)
+template <typename T>
+__global__ void fill_kernel(T *p, int64_t count, T v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
 
 // A(i, j) <- A(j, i) for i > j  (mirror the stored upper triangle into the lower)
-__global__ void mirror_upper_kernel(int64_t n, double *A, int64_t lda)
+template <typename T>
+__global__ void mirror_upper_kernel(int64_t n, T *A, int64_t lda)
 {
     const int64_t j = blockIdx.y;
     for (int64_t i = j + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -42,8 +41,9 @@ __global__ void mirror_upper_kernel(int64_t n, double *A, int64_t lda)
 // Copy the lower part of the diagonal blocks of the band into AB:
 // column j of panel block kb = (j / b) b covers rows j .. min(kb + b, n) - 1;
 // columns of the final (tail) block extend to row n - 1.
-__global__ void extract_diag_blocks_kernel(int64_t n, int64_t b, int64_t tail0, const double *A, int64_t lda,
-                                           double *AB, int64_t ldab)
+template <typename T>
+__global__ void extract_diag_blocks_kernel(int64_t n, int64_t b, int64_t tail0, const T *A, int64_t lda, T *AB,
+                                           int64_t ldab)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
     if (j >= n) return;
@@ -52,28 +52,28 @@ __global__ void extract_diag_blocks_kernel(int64_t n, int64_t b, int64_t tail0, 
     for (int64_t d = threadIdx.x; j + d < limit; d += blockDim.x) AB[d + j * ldab] = A[j + d + j * lda];
 }
 
-template <int B>
-__global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, double *P, int64_t lda,
-                                                                 double *YZY, int64_t ldy, double *part,
-                                                                 double *Sg, double *taus, double *Tout,
-                                                                 double *AB, int64_t ldab, int64_t j0)
+template <int B, typename T>
+__global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, T *P, int64_t lda,
+                                                                 T *YZY, int64_t ldy, T *part,
+                                                                 T *Sg, T *taus, T *Tout,
+                                                                 T *AB, int64_t ldab, int64_t j0, int *bar)
 {
     // part layout (G workgroups): [0, G) norms; [G] x0; [G+1, G+1+B) reduced
     // dots w; then B*G partial dots, column-major by column q: part[D0 + q*G + g].
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T *smem = (T *)smem_raw;
     const int ldp = chunk + 1;
-    double *Ps = smem;                 // Ps[q * ldp + i]: panel column q, local row i
-    __shared__ double wsh[B];
-    __shared__ double red[PANEL_THREADS / 64];
-    __shared__ double betas[B];
-    __shared__ double scal[4];
+    T *Ps = smem;                 // Ps[q * ldp + i]: panel column q, local row i
+    __shared__ T wsh[B];
+    __shared__ T red[PANEL_THREADS / 64];
+    __shared__ T betas[B];
+    __shared__ T scal[4];
 
-    cg::grid_group grid = cg::this_grid();
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
     const int64_t r0 = (int64_t)g * chunk;
     const int rows = (int)((m - r0) < chunk ? (m - r0) : chunk);
     const int nr = (int)(m < B ? m : B);
-    double *partN = part, *partX0 = part + G, *partW = part + G + 1, *partD = part + G + 1 + B;
+    T *partN = part, *partX0 = part + G, *partW = part + G + 1, *partD = part + G + 1 + B;
 
     for (int e = tid; e < rows * B; e += PANEL_THREADS) {
         const int i = e % rows, q = e / rows;
@@ -84,26 +84,25 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     constexpr int TPC = PANEL_THREADS / B;  // threads per column in the dot phase
     for (int j = 0; j < nr; ++j) {
         // ---- phase 1: partial sum of squares below row j
-        double ss = 0.0;
+        T ss = 0.0;
         for (int i = tid; i < rows; i += PANEL_THREADS)
-            if (r0 + i > j) { const double x = Ps[j * ldp + i]; ss += x * x; }
+            if (r0 + i > j) { const T x = Ps[j * ldp + i]; ss += x * x; }
         ss = block_sum(ss, red);
         if (tid == 0) {
-            partN[g] = ss;
-            if (g == 0) partX0[0] = Ps[j * ldp + j];  // row j lives in chunk 0
+            st_coh(&partN[g], ss);
+            if (g == 0) st_coh(&partX0[0], Ps[j * ldp + j]);  // row j lives in chunk 0
         }
-        __threadfence();
-        grid.sync();
+        grid_barrier_coh(bar, G);
 
         // ---- phase 2: Householder vector of column j, partial dots
-        double sig = 0.0;
-        for (int h = tid; h < G; h += PANEL_THREADS) sig += partN[h];
+        T sig = 0.0;
+        for (int h = tid; h < G; h += PANEL_THREADS) sig += ld_coh(&partN[h]);
         sig = block_sum(sig, red);
         if (tid == 0) {
-            const double x0 = partX0[0];
-            double tau = 0.0, beta = x0, scale = 0.0;
+            const T x0 = ld_coh(&partX0[0]);
+            T tau = 0.0, beta = x0, scale = 0.0;
             if (sig != 0.0) {
-                const double nrm = sqrt(x0 * x0 + sig);
+                const T nrm = sqrt(x0 * x0 + sig);
                 beta = (x0 >= 0.0) ? -nrm : nrm;
                 tau = (beta - x0) / beta;
                 scale = 1.0 / (x0 - beta);
@@ -113,7 +112,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
             scal[2] = scale;
         }
         __syncthreads();
-        const double tau = scal[0], scale = scal[2];
+        const T tau = scal[0], scale = scal[2];
         for (int i = tid; i < rows; i += PANEL_THREADS) {
             const int64_t gi = r0 + i;
             if (gi > j) Ps[j * ldp + i] *= scale;
@@ -123,34 +122,32 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
         __syncthreads();
         {
             const int q = tid % B, sub = tid / B;
-            double acc = 0.0;
+            T acc = 0.0;
             if (q != j)
                 for (int i = sub; i < rows; i += TPC)
                     if (r0 + i >= j) acc += Ps[j * ldp + i] * Ps[q * ldp + i];
             Ps[B * ldp + tid] = acc;  // scratch after the panel columns
             __syncthreads();
             if (tid < B) {
-                double s = 0.0;
+                T s = 0.0;
                 for (int t = 0; t < TPC; ++t) s += Ps[B * ldp + tid + t * B];
-                partD[(int64_t)tid * G + g] = s;
+                st_coh(&partD[(int64_t)tid * G + g], s);
             }
         }
-        __threadfence();
-        grid.sync();
+        grid_barrier_coh(bar, G);
 
         // ---- phase 3a: workgroup g reduces the partial dots of columns g, g+G, ...
         for (int q = g; q < B; q += G) {
-            double s = 0.0;
-            for (int h = tid; h < G; h += PANEL_THREADS) s += partD[(int64_t)q * G + h];
+            T s = 0.0;
+            for (int h = tid; h < G; h += PANEL_THREADS) s += ld_coh(&partD[(int64_t)q * G + h]);
             s = block_sum(s, red);
-            if (tid == 0) partW[q] = s;
+            if (tid == 0) st_coh(&partW[q], s);
         }
-        __threadfence();
-        grid.sync();
+        grid_barrier_coh(bar, G);
 
         // ---- phase 3b: update the remaining columns of the chunk
         if (tid < B) {
-            const double s = partW[tid];
+            const T s = ld_coh(&partW[tid]);
             wsh[tid] = s;
             if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = s;  // (Y[:, 0:j]^T v_j)
         }
@@ -170,7 +167,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     for (int e = tid; e < rows * B; e += PANEL_THREADS) {
         const int i = e % rows, q = e / rows;
         const int64_t gi = r0 + i;
-        double y = 0.0;
+        T y = 0.0;
         if (q < nr) y = (gi > q) ? Ps[q * ldp + i] : (gi == q ? 1.0 : 0.0);
         P[gi + (int64_t)q * lda] = y;
         YZY[gi + (int64_t)q * ldy] = y;
@@ -181,19 +178,19 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     for (int e = tid; e < B * B; e += PANEL_THREADS) {
         const int p = e % B, q = e / B;
         if (p <= q) {
-            const double v = (p >= nr) ? 0.0 : ((p == q) ? betas[q] : Ps[q * ldp + p]);
+            const T v = (p >= nr) ? 0.0 : ((p == q) ? betas[q] : Ps[q * ldp + p]);
             AB[(B + p - q) + (j0 + q) * ldab] = v;
         }
     }
     __syncthreads();
     // T factor in LDS (reuse the panel area), then out
-    double *Ts = smem;
+    T *Ts = smem;
     for (int e = tid; e < B * B; e += PANEL_THREADS) Ts[e] = 0.0;
     __syncthreads();
     for (int j = 0; j < B; ++j) {
-        const double tj = (j < nr) ? taus[j] : 0.0;
+        const T tj = (j < nr) ? taus[j] : 0.0;
         if (tid < j) {
-            double s = 0.0;
+            T s = 0.0;
             for (int r = tid; r < j; ++r) s += Ts[tid + r * B] * Sg[r + (int64_t)j * B];
             Ts[tid + j * B] = -tj * s;
         }
@@ -203,65 +200,69 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     for (int e = tid; e < B * B; e += PANEL_THREADS) Tout[e] = Ts[e];
 }
 
-template <int B>
-evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, double *P, int64_t lda, double *YZY, int64_t ldy, double *part,
-                          double *Sg, double *taus, double *Tout, double *AB, int64_t ldab, int64_t j0)
+template <int B, typename T>
+evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *YZY, int64_t ldy, T *part,
+                          T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar)
 {
     int maxg = 256;
+    if (ctx->panel_wgs > 0 && ctx->panel_wgs < maxg) maxg = (int)ctx->panel_wgs;
     int64_t chunk = evd_ceil_div(m, maxg);
     if (chunk < B) chunk = B;
     chunk = evd_ceil_div(chunk, 16) * 16;
     int G = (int)evd_ceil_div(m, chunk);
     // LDS: B columns plus one scratch column of PANEL_THREADS doubles
     int64_t ldp = chunk + 1;
-    size_t lds = (size_t)(B * ldp + (ldp > PANEL_THREADS ? ldp : PANEL_THREADS)) * sizeof(double);
-    if (lds < (size_t)B * B * sizeof(double)) lds = (size_t)B * B * sizeof(double);
+    size_t lds = (size_t)(B * ldp + (ldp > PANEL_THREADS ? ldp : PANEL_THREADS)) * sizeof(T);
+    if (lds < (size_t)B * B * sizeof(T)) lds = (size_t)B * B * sizeof(T);
     if (lds > 150 * 1024) return EVD_ERR_INVALID_ARG;
     int chunk_i = (int)chunk;
     void *args[] = {&m, &chunk_i, &P, (void *)&lda, &YZY, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
-                    (void *)&ldab, (void *)&j0};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B>, dim3(G), dim3(PANEL_THREADS), args,
+                    (void *)&ldab, (void *)&j0, &bar};
+    hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3(G), dim3(PANEL_THREADS), args,
                                               (unsigned)lds, ctx->stream);
     return e == hipSuccess ? EVD_OK : EVD_ERR_HIP;
 }
 
-evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, double *P, int64_t lda, double *YZY, int64_t ldy,
-                            double *part, double *Sg, double *taus, double *Tout, double *AB, int64_t ldab,
-                            int64_t j0)
+template <typename T>
+evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, T *P, int64_t lda, T *YZY, int64_t ldy, T *part,
+                            T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar)
 {
     switch (b) {
-    case 1: return launch_panel<1>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
-    case 2: return launch_panel<2>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
-    case 4: return launch_panel<4>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
-    case 8: return launch_panel<8>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
-    case 16: return launch_panel<16>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
-    case 32: return launch_panel<32>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
-    case 64: return launch_panel<64>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0);
+    case 1: return launch_panel<1, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
+    case 2: return launch_panel<2, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
+    case 4: return launch_panel<4, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
+    case 8: return launch_panel<8, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
+    case 16: return launch_panel<16, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
+    case 32: return launch_panel<32, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
+    case 64: return launch_panel<64, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
     default: return EVD_ERR_INVALID_ARG;
     }
 }
 
+template <typename T>
 struct SbrWork {
-    double *YZY;   // n x 3b
-    double *X;     // unused (Z is formed in place)
-    double *W;     // n x b
-    double *M;     // b x b
-    double *part;  // (257) x (b + 1)
-    double *Sg;    // b x b
-    double *taus;  // b
-    double *gemm_ws;
+    T *YZY;   // n x 3b
+    T *X;     // unused (Z is formed in place)
+    T *W;     // n x b
+    T *M;     // b x b
+    T *part;  // reduction scratch of the panel kernel
+    T *Sg;    // b x b
+    T *taus;  // b
+    T *gemm_ws;
     size_t gemm_ws_elems;
+    int *bar;  // grid barrier state of the panel kernel
 };
 
-size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork *w)
+template <typename T>
+size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
 {
     size_t off = 0;
     auto take = [&](size_t elems) {
         char *p = base ? base + off : nullptr;
-        off += evd_align256(elems * sizeof(double));
-        return (double *)p;
+        off += evd_align256(elems * sizeof(T));
+        return (T *)p;
     };
-    SbrWork t;
+    SbrWork<T> t;
     t.YZY = take((size_t)n * 3 * b);
     t.W = take((size_t)n * b);
     t.M = take((size_t)b * b);
@@ -270,13 +271,61 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork *w)
     t.taus = take((size_t)b);
     t.X = nullptr;
     // split-K workspace for the b x b product W^T Z (K up to n)
-    size_t ws = gemm_splitk_ws_elems(b, b, n);
-    size_t ws2 = gemm_splitk_ws_elems(n, b, n);
+    size_t ws = gemm_ws_elems_t<T>(b, b, n);
+    size_t ws2 = gemm_ws_elems_t<T>(n, b, n);
     if (ws2 > ws) ws = ws2;
     t.gemm_ws = take(ws);
     t.gemm_ws_elems = ws;
+    t.bar = (int *)take(64 / sizeof(T));
     if (w) *w = t;
     return off;
+}
+
+template <typename T>
+evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int64_t lda, T *AB, int64_t ldab,
+                       T *Tf, void *work)
+{
+    hipStream_t s = ctx->stream;
+    SbrWork<T> w;
+    sbr_layout<T>(n, b, (char *)work, &w);
+    if (uplo == 'U' || uplo == 'u') {
+        dim3 grid((unsigned)evd_ceil_div(n, 256) < 64 ? (unsigned)evd_ceil_div(n, 256) : 64u, (unsigned)n);
+        hipLaunchKernelGGL(mirror_upper_kernel<T>, grid, dim3(256), 0, s, n, A, lda);
+    }
+    {
+        const int64_t cnt = ldab * n;
+        hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)(evd_ceil_div(cnt, 256) < 4096 ? evd_ceil_div(cnt, 256) : 4096)),
+                           dim3(256), 0, s, AB, cnt, (T)0);
+    }
+    hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(64), 0, s, w.bar, (int64_t)2, 0);
+    const int64_t p = evd_sbr_num_panels(n, b);
+    for (int64_t k = 0; k < p; ++k) {
+        const int64_t j0 = k * b, i0 = j0 + b, m = n - i0;
+        T *P = A + i0 + j0 * lda;
+        T *A2 = A + i0 + i0 * lda;
+        T *Tk = Tf + k * b * b;
+        const int64_t ldy = m;
+        EVD_CHECK(panel_dispatch<T>(ctx, b, m, P, lda, w.YZY, ldy, w.part, w.Sg, w.taus, Tk, AB, ldab, j0, w.bar));
+        T *Y = w.YZY, *Zs = w.YZY + b * ldy;
+        // W = Y T
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)1, Y, ldy, Tk, b, (T)0, w.W, m, (T *)nullptr, 0));
+        // X = A_2 W  (into the Z slot)
+        EVD_CHECK(gemm_t(s, OP_S, OP_N, 0, m, b, m, (T)1, A2, lda, w.W, m, (T)0, Zs, ldy, w.gemm_ws,
+                           w.gemm_ws_elems));
+        // M = W^T X
+        EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, b, b, m, (T)1, w.W, m, Zs, ldy, (T)0, w.M, b, w.gemm_ws,
+                           w.gemm_ws_elems));
+        // Z = X - 1/2 Y M
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)-0.5, Y, ldy, w.M, b, (T)1, Zs, ldy, (T *)nullptr, 0));
+        // A_2 <- A_2 - [Y Z] [Z Y]^T   (lower triangle)
+        EVD_CHECK(gemm_t(s, OP_N, OP_T, 1, m, m, 2 * b, (T)-1, w.YZY, ldy, Zs, ldy, (T)1, A2, lda, (T *)nullptr, 0));
+    }
+    {
+        dim3 blk(64, 4);
+        hipLaunchKernelGGL(extract_diag_blocks_kernel<T>, dim3((unsigned)evd_ceil_div(n, 4)), blk, 0, s, n, b, p * b,
+                           (const T *)A, lda, AB, ldab);
+    }
+    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
 }
 
 }  // namespace
@@ -284,49 +333,17 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork *w)
 evd_status_t sbr_run(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda, double *AB,
                      int64_t ldab, double *T, void *work)
 {
-    hipStream_t s = ctx->stream;
-    SbrWork w;
-    sbr_layout(n, b, (char *)work, &w);
-    if (uplo == 'U' || uplo == 'u') {
-        dim3 grid((unsigned)evd_ceil_div(n, 256) < 64 ? (unsigned)evd_ceil_div(n, 256) : 64u, (unsigned)n);
-        hipLaunchKernelGGL(mirror_upper_kernel, grid, dim3(256), 0, s, n, A, lda);
-    }
-    {
-        const int64_t cnt = ldab * n;
-        hipLaunchKernelGGL(fill_kernel, dim3((unsigned)(evd_ceil_div(cnt, 256) < 4096 ? evd_ceil_div(cnt, 256) : 4096)),
-                           dim3(256), 0, s, AB, cnt, 0.0);
-    }
-    const int64_t p = evd_sbr_num_panels(n, b);
-    for (int64_t k = 0; k < p; ++k) {
-        const int64_t j0 = k * b, i0 = j0 + b, m = n - i0;
-        double *P = A + i0 + j0 * lda;
-        double *A2 = A + i0 + i0 * lda;
-        double *Tk = T + k * b * b;
-        const int64_t ldy = m;
-        EVD_CHECK(panel_dispatch(ctx, b, m, P, lda, w.YZY, ldy, w.part, w.Sg, w.taus, Tk, AB, ldab, j0));
-        double *Y = w.YZY, *Zs = w.YZY + b * ldy;
-        // W = Y T
-        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, m, b, b, 1.0, Y, ldy, Tk, b, 0.0, w.W, m, nullptr, 0));
-        // X = A_2 W  (into the Z slot)
-        EVD_CHECK(gemm_f64(s, OP_S, OP_N, 0, m, b, m, 1.0, A2, lda, w.W, m, 0.0, Zs, ldy, w.gemm_ws,
-                           w.gemm_ws_elems));
-        // M = W^T X
-        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, b, b, m, 1.0, w.W, m, Zs, ldy, 0.0, w.M, b, w.gemm_ws,
-                           w.gemm_ws_elems));
-        // Z = X - 1/2 Y M
-        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, m, b, b, -0.5, Y, ldy, w.M, b, 1.0, Zs, ldy, nullptr, 0));
-        // A_2 <- A_2 - [Y Z] [Z Y]^T   (lower triangle)
-        EVD_CHECK(gemm_f64(s, OP_N, OP_T, 1, m, m, 2 * b, -1.0, w.YZY, ldy, Zs, ldy, 1.0, A2, lda, nullptr, 0));
-    }
-    {
-        dim3 blk(64, 4);
-        hipLaunchKernelGGL(extract_diag_blocks_kernel, dim3((unsigned)evd_ceil_div(n, 4)), blk, 0, s, n, b, p * b,
-                           (const double *)A, lda, AB, ldab);
-    }
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return sbr_run_t<double>(ctx, uplo, n, b, A, lda, AB, ldab, T, work);
 }
 
-size_t sbr_work_bytes(int64_t n, int64_t b) { return sbr_layout(n, b, nullptr, nullptr); }
+evd_status_t sbr_run_f32(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, float *A, int64_t lda, float *AB,
+                         int64_t ldab, float *T, void *work)
+{
+    return sbr_run_t<float>(ctx, uplo, n, b, A, lda, AB, ldab, T, work);
+}
+
+size_t sbr_work_bytes(int64_t n, int64_t b) { return sbr_layout<double>(n, b, nullptr, nullptr); }
+size_t sbr_work_bytes_f32(int64_t n, int64_t b) { return sbr_layout<float>(n, b, nullptr, nullptr); }
 
 extern "C" {
 

@@ -38,8 +38,19 @@ PROTOTYPES = {
     "evd_get_stage_times": (_st, [_vp, ctypes.POINTER(ctypes.c_float)]),
     "evd_dgemm": (_st, [_vp, _c, _c, _i32, _i64, _i64, _i64, _d, _vp, _i64, _vp, _i64, _d, _vp, _i64, _vp, _sz]),
     "evd_dgemm_work_size": (_st, [_vp, _i64, _i64, _i64, ctypes.POINTER(_sz)]),
+    "evd_sgemm_x3": (_st, [_vp, _c, _c, _i32, _i64, _i64, _i64, ctypes.c_float, _vp, _i64, _vp, _i64,
+                           ctypes.c_float, _vp, _i64, _vp, _sz]),
+    "evd_sgemm_x3_work_size": (_st, [_vp, _i64, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dsyevd_work_size": (_st, [_vp, _c, _c, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dsyevd": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "evd_dsyevd_mixed_work_size": (_st, [_vp, _c, _c, _i64, _i64, ctypes.POINTER(_sz)]),
+    "evd_dsyevd_mixed": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _i32, _vp, _sz, _vp, _vp]),
+    "evd_autotune_work_size": (_st, [_vp, _c, _i64, ctypes.POINTER(_sz)]),
+    "evd_autotune": (_st, [_vp, _c, _i64, _vp, _i64, _vp, _sz, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_float)]),
+    "evd_dsyevd_batched_work_size": (_st, [_vp, _c, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                           ctypes.POINTER(_sz)]),
+    "evd_dsyevd_batched": (_st, [_vp, _c, _c, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_vp),
+                                 ctypes.POINTER(_i64), ctypes.POINTER(_vp), _vp, _sz, _vp, _vp]),
     "evd_sbr_num_panels": (_i64, [_i64, _i64]),
     "evd_dsy2sb_work_size": (_st, [_vp, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dsy2sb": (_st, [_vp, _c, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz]),
@@ -152,6 +163,19 @@ class Context:
         self._check("evd_dgemm_work_size", self.lib.evd_dgemm_work_size(self.handle, m, n, k, ctypes.byref(b)))
         return b.value
 
+    def evd_sgemm_x3(self, opa, opb, lower_c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, work=None,
+                     work_bytes=0):
+        self.set_stream()
+        st = self.lib.evd_sgemm_x3(self.handle, _ch(opa), _ch(opb), int(lower_c), m, n, k, alpha, _ptr(A), lda,
+                                   _ptr(B), ldb, beta, _ptr(C), ldc, _ptr(work), work_bytes)
+        self._check("evd_sgemm_x3", st)
+
+    def evd_sgemm_x3_work_size(self, m, n, k) -> int:
+        b = _sz()
+        self._check("evd_sgemm_x3_work_size", self.lib.evd_sgemm_x3_work_size(self.handle, m, n, k,
+                                                                              ctypes.byref(b)))
+        return b.value
+
     def evd_dsyevd_work_size(self, jobz, uplo, n, lda) -> int:
         b = _sz()
         st = self.lib.evd_dsyevd_work_size(self.handle, _ch(jobz), _ch(uplo), n, lda, ctypes.byref(b))
@@ -163,6 +187,50 @@ class Context:
         st = self.lib.evd_dsyevd(self.handle, _ch(jobz), _ch(uplo), n, _ptr(A), lda, _ptr(W), _ptr(work),
                                  work_bytes, _ptr(info))
         self._check("evd_dsyevd", st)
+
+    def evd_dsyevd_mixed_work_size(self, jobz, uplo, n, lda) -> int:
+        b = _sz()
+        st = self.lib.evd_dsyevd_mixed_work_size(self.handle, _ch(jobz), _ch(uplo), n, lda, ctypes.byref(b))
+        self._check("evd_dsyevd_mixed_work_size", st)
+        return b.value
+
+    def evd_dsyevd_mixed(self, jobz, uplo, n, A, lda, W, sweeps, work, work_bytes, info, stats=None):
+        self.set_stream()
+        st = self.lib.evd_dsyevd_mixed(self.handle, _ch(jobz), _ch(uplo), n, _ptr(A), lda, _ptr(W), int(sweeps),
+                                       _ptr(work), work_bytes, _ptr(info), _ptr(stats))
+        self._check("evd_dsyevd_mixed", st)
+
+    def evd_autotune_work_size(self, jobz, n) -> int:
+        b = _sz()
+        self._check("evd_autotune_work_size", self.lib.evd_autotune_work_size(self.handle, _ch(jobz), n,
+                                                                              ctypes.byref(b)))
+        return b.value
+
+    def evd_autotune(self, jobz, n, A, lda, work, work_bytes):
+        self.set_stream()
+        bb, ms = _i64(), ctypes.c_float()
+        st = self.lib.evd_autotune(self.handle, _ch(jobz), n, _ptr(A), lda, _ptr(work), work_bytes,
+                                   ctypes.byref(bb), ctypes.byref(ms))
+        self._check("evd_autotune", st)
+        return bb.value, ms.value
+
+    def evd_dsyevd_batched_work_size(self, jobz, ns, ldas) -> int:
+        k = len(ns)
+        na, la = (_i64 * max(k, 1))(*ns), (_i64 * max(k, 1))(*ldas)
+        b = _sz()
+        st = self.lib.evd_dsyevd_batched_work_size(self.handle, _ch(jobz), k, na, la, ctypes.byref(b))
+        self._check("evd_dsyevd_batched_work_size", st)
+        return b.value
+
+    def evd_dsyevd_batched(self, jobz, uplo, ns, As, ldas, Ws, work, work_bytes, info, stamps=None):
+        self.set_stream()
+        k = len(ns)
+        na, la = (_i64 * max(k, 1))(*ns), (_i64 * max(k, 1))(*ldas)
+        ap = (_vp * max(k, 1))(*[_ptr(a) for a in As])
+        wp = (_vp * max(k, 1))(*[_ptr(w) for w in Ws])
+        st = self.lib.evd_dsyevd_batched(self.handle, _ch(jobz), _ch(uplo), k, na, ap, la, wp, _ptr(work),
+                                         work_bytes, _ptr(info), _ptr(stamps))
+        self._check("evd_dsyevd_batched", st)
 
     def evd_dsy2sb_work_size(self, n, b) -> int:
         s = _sz()
@@ -229,6 +297,27 @@ def context(device: int = 0) -> Context:
     if device not in _default_ctx:
         _default_ctx[device] = Context(device)
     return _default_ctx[device]
+
+
+def eigh_mixed(A, sweeps: int = 2, uplo: str = "L", b: int = 0, ctx: Context | None = None):
+    """``evd_dsyevd_mixed`` on a float64 GPU tensor: returns (w, Q, stats)."""
+    import torch
+
+    n = A.shape[0]
+    ctx = ctx or context(A.device.index or 0)
+    if b:
+        ctx.set_param("b", b)
+    Acm = A.t().contiguous().t()
+    Acm = Acm.clone() if Acm.data_ptr() == A.data_ptr() else Acm
+    W = torch.empty(max(n, 1), dtype=torch.float64, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    stats = torch.zeros(8, dtype=torch.float64, device=A.device)
+    wb = ctx.evd_dsyevd_mixed_work_size("V", uplo, n, max(n, 1))
+    work = torch.empty(max(wb, 256) // 8 + 32, dtype=torch.float64, device=A.device)
+    ctx.evd_dsyevd_mixed("V", uplo, n, Acm, max(n, 1), W, sweeps, work, wb, info, stats)
+    if int(info.item()) != 0:
+        raise EvdError("evd_dsyevd_mixed", EVD_ERR_NOT_CONVERGED, int(info.item()))
+    return W[:n], Acm, stats
 
 
 def eigh(A, jobz: str = "V", uplo: str = "L", b: int = 0, ctx: Context | None = None):
