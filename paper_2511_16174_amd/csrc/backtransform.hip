@@ -95,21 +95,21 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
                 load_group(buf ^ 1, c0, s - 1);
             }
             // apply the G reflectors of step s, sweeps ascending
-#pragma unroll
+#pragma clang loop unroll(full)
             for (int jj = 0; jj < G; ++jj) {
                 const T tau = ts[buf][jj];
                 const T *v = &vs[buf][jj][VPAD + rho - jj];
                 constexpr int CNT = B / 4 + 1;
                 const int k0 = jj / 4;
                 T d0 = 0.0, d1 = 0.0;
-#pragma unroll
+#pragma clang loop unroll(full)
                 for (int q = 0; q < CNT; q += 2) {
                     const int k = k0 + q;
                     if (k < NW) d0 += x[k] * v[4 * k];
                     if (q + 1 < CNT && k + 1 < NW) d1 += x[k + 1] * v[4 * (k + 1)];
                 }
                 const T w = tau * quad_sum(d0 + d1);
-#pragma unroll
+#pragma clang loop unroll(full)
                 for (int q = 0; q < CNT; ++q) {
                     const int k = k0 + q;
                     if (k < NW) x[k] -= w * v[4 * k];
@@ -117,12 +117,12 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
             }
             // slide: columns leaving the window go back to memory
             if (s > 0) {
-#pragma unroll
+#pragma clang loop unroll(full)
                 for (int k = NW - SH; k < NW; ++k) {
                     const int64_t col = base + 4 * k + rho;
                     if (rowok && col < n) Qr[col * ldq] = x[k];
                 }
-#pragma unroll
+#pragma clang loop unroll(full)
                 for (int k = NW - 1; k >= SH; --k) x[k] = x[k - SH];
 #pragma unroll
                 for (int k = 0; k < SH; ++k) x[k] = pre[k];
@@ -223,11 +223,76 @@ evd_status_t bcback_run_f32(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, 
     return bcback_run_t<float>(ctx, mrows, n, b, V, TAU, Q, ldq);
 }
 
-size_t orgsb_work_bytes(int64_t n, int64_t b) { return evd_align256((size_t)2 * b * (n > 0 ? n : 1) * 8); }
+// SBR-back.  Q_s = H^(0) H^(1) ... H^(p-1), H^(k) = I - Y_k T_k Y_k^T acting on
+// rows/cols (k+1)b .. n-1, accumulated backwards on the identity.  Panels are
+// aggregated ORGSB_NB columns at a time into one block reflector
+// I - Y_g T_g Y_g^T (T_g from the recurrence T = [[T1, -T1 Y1^T Y2 T2], [0, T2]]),
+// so the two large products of each group have inner dimension ORGSB_NB
+// rather than b.
+constexpr int64_t ORGSB_NB = 256;
 
-// Q_s = H^(0) H^(1) ... H^(p-1), H^(k) = I - Y_k T_k Y_k^T on rows/cols (k+1)b .. n-1,
-// accumulated backwards on the identity.
 namespace {
+
+int64_t orgsb_group_panels(int64_t b) { return (ORGSB_NB / b) > 0 ? ORGSB_NB / b : 1; }
+
+template <typename T>
+struct OrgsbWork {
+    T *Yg, *S, *Tg, *X1, *W1, *W2, *ws;
+    size_t ws_elems;
+};
+
+template <typename T>
+size_t orgsb_layout(int64_t n, int64_t b, char *base, OrgsbWork<T> *w)
+{
+    const int64_t nb = orgsb_group_panels(b) * b;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    size_t off = 0;
+    auto take = [&](size_t elems) {
+        char *p = base ? base + off : nullptr;
+        off += evd_align256(elems * sizeof(T));
+        return (T *)p;
+    };
+    OrgsbWork<T> t;
+    t.Yg = take(nn * nb);
+    t.S = take((size_t)nb * nb);
+    t.Tg = take((size_t)nb * nb);
+    t.X1 = take((size_t)nb * b);
+    t.W1 = take((size_t)nb * nn);
+    t.W2 = take((size_t)nb * nn);
+    t.ws_elems = gemm_ws_elems_t<T>(nb, nb, n);
+    t.ws = take(t.ws_elems > 0 ? t.ws_elems : 1);
+    if (w) *w = t;
+    return off;
+}
+
+// Yg(r, c) = Y_{k0 + c/b}(row i0 + r, column c % b), zero above that panel's rows.
+template <typename T>
+__global__ void orgsb_gather_y_kernel(int64_t m, int64_t nbw, int64_t b, int64_t i0, int64_t k0, const T *A,
+                                      int64_t lda, T *Yg)
+{
+    const int64_t total = m * nbw;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx % m, c = idx / m;
+        const int64_t kp = k0 + c / b;
+        const int64_t gi = i0 + r;
+        Yg[idx] = (gi >= kp * b + b) ? A[gi + (kp * b + c % b) * lda] : (T)0;
+    }
+}
+
+// Tg <- 0 with the panels' T factors on its diagonal blocks.
+template <typename T>
+__global__ void orgsb_diag_t_kernel(int64_t nbw, int64_t ldt, int64_t b, int64_t k0, const T *Tf, T *Tg)
+{
+    const int64_t total = nbw * nbw;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx % nbw, c = idx / nbw;
+        const int64_t pr = r / b, pc = c / b;
+        Tg[r + c * ldt] = (pr == pc) ? Tf[(k0 + pc) * b * b + (r % b) + (c % b) * b] : (T)0;
+    }
+}
+
 template <typename T>
 evd_status_t orgsb_run_t(evd_ctx_t ctx, int64_t n, int64_t b, const T *A, int64_t lda, const T *Tf, T *Q,
                          int64_t ldq, void *work)
@@ -235,22 +300,50 @@ evd_status_t orgsb_run_t(evd_ctx_t ctx, int64_t n, int64_t b, const T *A, int64_
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(eye_kernel<T>, dim3((unsigned)(evd_ceil_div(n * n, 256) < 8192 ? evd_ceil_div(n * n, 256) : 8192)),
                        dim3(256), 0, s, n, Q, ldq);
-    T *W1 = (T *)work;
-    T *W2 = W1 + (size_t)b * n;
+    OrgsbWork<T> w;
+    orgsb_layout<T>(n, b, (char *)work, &w);
     const int64_t p = evd_sbr_num_panels(n, b);
-    for (int64_t k = p - 1; k >= 0; --k) {
-        const int64_t j0 = k * b, i0 = j0 + b, m = n - i0;
-        const T *Y = A + i0 + j0 * lda;
+    const int64_t gp = orgsb_group_panels(b);
+    const int64_t nb = gp * b;
+    const int64_t ngroups = evd_ceil_div(p, gp);
+    for (int64_t g = ngroups - 1; g >= 0; --g) {
+        const int64_t k0 = g * gp;
+        const int64_t np = (k0 + gp <= p) ? gp : p - k0;
+        const int64_t nbw = np * b;
+        const int64_t i0 = k0 * b + b, m = n - i0;
         T *Qs = Q + i0 + i0 * ldq;
-        // W1 = Y^T Q_sub (b x m);  W2 = T W1;  Q_sub -= Y W2
-        EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, b, m, m, (T)1, Y, lda, Qs, ldq, (T)0, W1, b, (T *)nullptr, 0));
-        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, b, m, b, (T)1, Tf + k * b * b, b, W1, b, (T)0, W2, b, (T *)nullptr, 0));
-        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, m, b, (T)-1, Y, lda, W2, b, (T)1, Qs, ldq, (T *)nullptr, 0));
+        const int64_t blocks_y = evd_ceil_div(m * nbw, 256) < 8192 ? evd_ceil_div(m * nbw, 256) : 8192;
+        hipLaunchKernelGGL(orgsb_gather_y_kernel<T>, dim3((unsigned)blocks_y), dim3(256), 0, s, m, nbw, b, i0, k0, A,
+                           lda, w.Yg);
+        hipLaunchKernelGGL(orgsb_diag_t_kernel<T>, dim3((unsigned)evd_ceil_div(nbw * nbw, 256)), dim3(256), 0, s, nbw,
+                           nb, b, k0, Tf, w.Tg);
+        if (np > 1) {
+            // S = Yg^T Yg, then the off-diagonal blocks of T_g panel by panel
+            EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, nbw, nbw, m, (T)1, w.Yg, m, w.Yg, m, (T)0, w.S, nb, w.ws, w.ws_elems));
+            for (int64_t i = 1; i < np; ++i) {
+                const int64_t cur = i * b;
+                EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, cur, b, cur, (T)1, w.Tg, nb, w.S + cur * nb, nb, (T)0, w.X1, nb,
+                                 (T *)nullptr, 0));
+                EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, cur, b, b, (T)-1, w.X1, nb, Tf + (k0 + i) * b * b, b, (T)0,
+                                 w.Tg + cur * nb, nb, (T *)nullptr, 0));
+            }
+        }
+        // W1 = Yg^T Q_sub;  W2 = T_g W1;  Q_sub -= Yg W2
+        EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, nbw, m, m, (T)1, w.Yg, m, Qs, ldq, (T)0, w.W1, nb, (T *)nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, nbw, m, nbw, (T)1, w.Tg, nb, w.W1, nb, (T)0, w.W2, nb, (T *)nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, m, nbw, (T)-1, w.Yg, m, w.W2, nb, (T)1, Qs, ldq, (T *)nullptr, 0));
     }
     return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
 }
 
 }  // namespace
+
+size_t orgsb_work_bytes(int64_t n, int64_t b)
+{
+    const size_t a = orgsb_layout<double>(n, b, nullptr, nullptr);
+    const size_t f = orgsb_layout<float>(n, b, nullptr, nullptr);
+    return a > f ? a : f;
+}
 
 evd_status_t orgsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *Q,
                        int64_t ldq, void *work)

@@ -18,12 +18,15 @@
 // them, with every earlier sweep.  Step (c, s) may therefore run as soon as
 // sweep c-1 has finished step s+1 (or all of its steps).
 //
-// Execution: one persistent launch; a one-wavefront workgroup owns sweeps
-// c = g, g+P, g+2P, ... and keeps its E and D windows in LDS (lane p = row p
-// of the window).  Band entries are read and written with device-coherent
-// (sc1) accesses; progress counters prog[c] (steps finished) are published
-// after the wavefront's stores have drained and polled the same way, so no
-// step needs a whole-cache writeback or invalidation.
+// Execution: one persistent launch; a workgroup of four threads per window
+// row owns sweeps c = g, g+P, g+2P, ... and stages each step's E and D windows
+// in LDS.  All band loads of a step are issued together (one memory latency
+// per step), row and column products run as quad-parallel dot products
+// reduced with DPP, and the Householder vector is formed by one wavefront.
+// Band entries are read and written with device-coherent (sc1) accesses;
+// progress counters prog[c] (steps finished) are published after every
+// wavefront's stores have drained and polled the same way, so no step needs a
+// whole-cache writeback or invalidation.
 #include "common.h"
 
 namespace {
@@ -63,22 +66,34 @@ __device__ __forceinline__ void bc_house(T x, int lane, int m, T *v, T *tau, T *
     *v = (lane == 0) ? 1.0 : ((lane < m) ? x * scale : 0.0);
 }
 
+// Threads per workgroup: four per window row (at least one wavefront).
+__host__ __device__ constexpr int bc_threads(int B) { return 4 * B < 64 ? 64 : 4 * B; }
+
 template <int B, typename T>
-__global__ __launch_bounds__(64) void bc_kernel(int64_t n, T *AB, int64_t ldab, T *V, T *TAU,
-                                                int *prog, int store_v)
+__global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int64_t ldab, T *V, T *TAU,
+                                                           int *prog, int store_v)
 {
+    constexpr int NT = bc_threads(B);
+    constexpr int NW = NT / 64;
     constexpr int LDW = B + 1;
+    constexpr int KL = (B * B + NT - 1) / NT;  // window elements per thread (coalesced column loads)
     __shared__ T Es[B * LDW];
     __shared__ T Ds[B * LDW];
-    __shared__ T vs[B];
+    __shared__ T vs[B];   // current reflector
+    __shared__ T vps[B];  // previous reflector of the sweep
     __shared__ T ws[B];
+    __shared__ T red[NW];
+    __shared__ T sh_tb[2];
 
-    const int lane = threadIdx.x;
-    const bool act = lane < B;  // lanes that own a window row
-    for (int e = lane; e < B * LDW; e += 64) {
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int p = t >> 2, rho = t & 3;  // quad-parallel phases: row (or column) p, quarter rho
+    const bool own = p < B;
+    for (int e = t; e < B * LDW; e += NT) {
         Es[e] = (T)0;
         Ds[e] = (T)0;
     }
+    if (t < B) vps[t] = (T)0;
     __syncthreads();
     const int64_t P = gridDim.x;
     const int64_t nsweeps = n - 2;
@@ -86,111 +101,133 @@ __global__ __launch_bounds__(64) void bc_kernel(int64_t n, T *AB, int64_t ldab, 
     for (int64_t c = blockIdx.x; c < nsweeps; c += P) {
         const int64_t S = bc_steps(n, c, B);
         const int64_t Sprev = (c > 0) ? bc_steps(n, c - 1, B) : 0;
-        T vprev = 0.0, tprev = 0.0;  // previous reflector of this sweep (lane entry)
+        T tprev = 0.0;
         for (int64_t s = 0; s < S; ++s) {
             // wait for sweep c-1 to finish step s+1 (or all of its steps)
             if (c > 0) {
-                // the acquire load invalidates this CU's caches for the data
-                // sweep c-1 published before its release store
                 const int need = (int)((s + 2 < Sprev) ? s + 2 : Sprev);
-                if (lane == 0)
+                if (t == 0)
                     while (ld_coh(&prog[c - 1]) < need) __builtin_amdgcn_s_sleep(1);
                 __syncthreads();
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
             }
             const int64_t r = c + 1 + s * B;
+            const int64_t rp = r - B;
             const int m = (int)((n - r) < B ? (n - r) : B);
-            T v = 0.0, tau = 0.0, beta = 0.0;
-            if (s == 0) {
-                const T x = (lane < m) ? ld_coh(&AB[(1 + lane) + c * ldab]) : (T)0;
-                bc_house(x, lane, m, &v, &tau, &beta);
-                if (lane < m) st_coh(&AB[(1 + lane) + c * ldab], (lane == 0) ? beta : (T)0);
-            } else {
-                const int64_t rp = r - B;
-                // E (m x B): rows r.., columns rp..; receives H_{s-1} from the right
-                if (act) {
-                    for (int q = 0; q < B; ++q)
-                        Es[lane * LDW + q] = (lane < m) ? ld_coh(&AB[(B + lane - q) + (rp + q) * ldab]) : (T)0;
-                    vs[lane] = vprev;
+
+            // every window load of the step is issued before any is consumed:
+            // element k*NT + t is (row, col) = (idx % B, idx / B), so a
+            // wavefront reads whole band columns
+            // (E and D share the 32-bit in-window offset (row - col) + col*ldab)
+            T x = 0.0;
+            T eb[KL], db[KL];
+            T *const Eb = AB + rp * ldab + B;
+            T *const Db = AB + r * ldab;
+            const int ld = (int)ldab;
+            if (s == 0 && wv == 0 && lane < m) x = ld_coh(&AB[(1 + lane) + c * ldab]);
+#pragma unroll
+            for (int k = 0; k < KL; ++k) {
+                const int idx = k * NT + t, row = idx % B, col = idx / B;
+                const int o = (row - col) + col * ld;
+                eb[k] = (s > 0 && col < B && row < m) ? ld_coh(Eb + o) : (T)0;
+                db[k] = (col < m && row < m && row >= col) ? ld_coh(Db + o) : (T)0;
+            }
+#pragma unroll
+            for (int k = 0; k < KL; ++k) {
+                const int idx = k * NT + t, row = idx % B, col = idx / B;
+                if (col < B) {
+                    if (s > 0) Es[row * LDW + col] = eb[k];
+                    if (row >= col) {
+                        Ds[row * LDW + col] = db[k];
+                        Ds[col * LDW + row] = db[k];
+                    }
                 }
-                __syncthreads();
-                if (tprev != 0.0 && lane < m) {
+            }
+            __syncthreads();
+
+            if (s > 0) {
+                // E receives H_{s-1} from the right: row p, columns q = rho (mod 4)
+                if (tprev != 0.0) {
                     T y = 0.0;
-                    for (int q = 0; q < B; ++q) y += Es[lane * LDW + q] * vs[q];
-                    y *= tprev;
-                    for (int q = 0; q < B; ++q) Es[lane * LDW + q] -= y * vs[q];
+                    if (own)
+                        for (int q = rho; q < B; q += 4) y += Es[p * LDW + q] * vps[q];
+                    y = quad_sum(y) * tprev;
+                    if (own)
+                        for (int q = rho; q < B; q += 4) Es[p * LDW + q] -= y * vps[q];
+                    __syncthreads();
                 }
-                __syncthreads();
-                // H_s from E's first column, applied from the left to columns 1..B-1
-                const T x = (lane < m) ? Es[lane * LDW + 0] : 0.0;
+                if (wv == 0) x = (lane < m) ? Es[lane * LDW + 0] : (T)0;
+            }
+            // H_s from x (wavefront 0)
+            if (wv == 0) {
+                T v, tau, beta;
                 bc_house(x, lane, m, &v, &tau, &beta);
-                if (act) vs[lane] = v;
-                __syncthreads();
-                if (tau != 0.0 && lane >= 1 && lane < B) {
-                    // rows >= m of E and entries >= m of v are zero
-                    const int q = lane;
+                if (lane < B) vs[lane] = v;
+                if (lane == 0) {
+                    sh_tb[0] = tau;
+                    sh_tb[1] = beta;
+                }
+                if (s == 0 && lane < m) st_coh(&AB[(1 + lane) + c * ldab], (lane == 0) ? beta : (T)0);
+            }
+            __syncthreads();
+            const T tau = sh_tb[0], beta = sh_tb[1];
+
+            if (s > 0) {
+                // H_s from the left on E's columns 1..B-1: column p, rows i = rho (mod 4)
+                if (tau != 0.0) {
                     T w = 0.0;
-#pragma unroll 16
-                    for (int p = 0; p < B; ++p) w += vs[p] * Es[p * LDW + q];
-                    w *= tau;
-#pragma unroll 16
-                    for (int p = 0; p < B; ++p) Es[p * LDW + q] -= vs[p] * w;
+                    if (own && p >= 1)
+                        for (int i = rho; i < B; i += 4) w += vs[i] * Es[i * LDW + p];
+                    w = quad_sum(w) * tau;
+                    if (own && p >= 1)
+                        for (int i = rho; i < B; i += 4) Es[i * LDW + p] -= vs[i] * w;
+                    __syncthreads();
                 }
-                __syncthreads();
-                if (lane < m) {
-                    Es[lane * LDW + 0] = (lane == 0) ? beta : 0.0;
-                    for (int q = 0; q < B; ++q) st_coh(&AB[(B + lane - q) + (rp + q) * ldab], Es[lane * LDW + q]);
+#pragma unroll
+                for (int k = 0; k < KL; ++k) {
+                    const int idx = k * NT + t, row = idx % B, col = idx / B;
+                    if (col < B && row < m) {
+                        const T val = (col == 0) ? ((row == 0) ? beta : (T)0) : Es[row * LDW + col];
+                        st_coh(Eb + ((row - col) + col * ld), val);
+                    }
                 }
             }
-            // D_s two-sided: D <- H D H
+            // D_s two-sided: D <- H D H with u = tau D v, w = u - (tau/2)(u.v) v
             if (tau != 0.0) {
-                if (act) vs[lane] = v;
-                // load the lower triangle column by column (coalesced, all loads
-                // in flight), then mirror into the full block
-                T dcol[B];
-#pragma unroll
-                for (int q = 0; q < B; ++q)
-                    dcol[q] = (q < m && lane < m && lane >= q) ? ld_coh(&AB[(lane - q) + (r + q) * ldab]) : (T)0;
-#pragma unroll
-                for (int q = 0; q < B; ++q) {
-                    if (q < m && lane < m && lane >= q) {
-                        Ds[lane * LDW + q] = dcol[q];
-                        Ds[q * LDW + lane] = dcol[q];
-                    }
-                }
-                __syncthreads();
                 T u = 0.0;
-                if (lane < m) {
-                    // entries of v beyond m are zero; stale finite D entries meet them
-#pragma unroll 16
-                    for (int q = 0; q < B; ++q) u += Ds[lane * LDW + q] * vs[q];
-                    u *= tau;
-                }
-                const T alpha = 0.5 * tau * wave_sum(lane < m ? u * v : (T)0);
-                const T w = u - alpha * v;
-                if (act) ws[lane] = w;
+                if (own)
+                    for (int q = rho; q < B; q += 4) u += Ds[p * LDW + q] * vs[q];
+                u = quad_sum(u) * tau;
+                const T vp = own ? vs[p] : (T)0;
+                const T a = wave_sum((own && rho == 0 && p < m) ? u * vp : (T)0);
+                if (lane == 0) red[wv] = a;
                 __syncthreads();
-                if (lane < m) {
+                T al = 0.0;
 #pragma unroll
-                    for (int q = 0; q < B; ++q) {
-                        if (q <= lane) {
-                            const T d = Ds[lane * LDW + q] - v * ws[q] - w * vs[q];
-                            st_coh(&AB[(lane - q) + (r + q) * ldab], d);
-                        }
+                for (int k = 0; k < NW; ++k) al += red[k];
+                al *= (T)0.5 * tau;
+                if (own && rho == 0) ws[p] = u - al * vp;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < KL; ++k) {
+                    const int idx = k * NT + t, row = idx % B, col = idx / B;
+                    if (col < m && row < m && row >= col) {
+                        const T d = Ds[row * LDW + col] - vs[row] * ws[col] - ws[row] * vs[col];
+                        st_coh(Db + ((row - col) + col * ld), d);
                     }
                 }
             }
-            if (store_v) {
-                if (act) V[((int64_t)s * n + c) * B + lane] = (lane < m) ? v : 0.0;
-                if (lane == 0) TAU[(int64_t)s * n + c] = tau;
+            if (t < B) {
+                if (store_v) V[((int64_t)s * n + c) * B + t] = vs[t];
+                vps[t] = vs[t];
             }
-            vprev = v;
+            if (store_v && t == 0) TAU[(int64_t)s * n + c] = tau;
             tprev = tau;
-            // publish: this wavefront's (coherent) stores complete before the
-            // counter (one wavefront per workgroup)
+            // publish: every wavefront's (coherent) stores complete before the
+            // counter moves
             mem_drain();
             __syncthreads();
-            if (lane == 0) st_coh(&prog[c], (int)(s + 1));
+            if (t == 0) st_coh(&prog[c], (int)(s + 1));
         }
     }
 }
@@ -218,7 +255,8 @@ evd_status_t bc_launch(evd_ctx_t ctx, int64_t n, T *AB, int64_t ldab, T *V, T *T
                        int store_v)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc_kernel<B, T>, 64, 0) != hipSuccess) return EVD_ERR_HIP;
+    constexpr int NT = bc_threads(B);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc_kernel<B, T>, NT, 0) != hipSuccess) return EVD_ERR_HIP;
     if (per_cu < 1) per_cu = 1;
     int64_t P = (int64_t)per_cu * ctx->num_cus;
     if (ctx->bc_waves > 0 && ctx->bc_waves < P) P = ctx->bc_waves;
@@ -226,7 +264,7 @@ evd_status_t bc_launch(evd_ctx_t ctx, int64_t n, T *AB, int64_t ldab, T *V, T *T
     if (P > nsweeps) P = nsweeps;
     if (P < 1) P = 1;
     void *args[] = {(void *)&n, &AB, (void *)&ldab, &V, &TAU, &prog, &store_v};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(64), args, 0,
+    hipError_t e = hipLaunchCooperativeKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args, 0,
                                               ctx->stream);
     return e == hipSuccess ? EVD_OK : EVD_ERR_HIP;
 }

@@ -214,6 +214,33 @@ struct GemmProblem {
 };
 evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob, int64_t max_m, int64_t max_n);
 
+// One K-slice of a GEMM operand tile is an LC x LS block in memory (LC
+// contiguous elements, lines ld apart).  Thread tid loads elements
+// e = tid + r*NT, (c, s) = (e % LC, e / LC), through a uniform base pointer and
+// 32-bit offsets; interior slices skip the bounds tests.
+template <typename T, int LC, int LS, int NT>
+struct TileSlice {
+    static constexpr int E = LC * LS / NT;
+    static_assert(E * NT == LC * LS, "slice/thread mismatch");
+    static __device__ __forceinline__ int c(int tid, int r) { return (tid + r * NT) % LC; }
+    static __device__ __forceinline__ int s(int tid, int r) { return (tid + r * NT) / LC; }
+    // full: every element in bounds; else c < cmax and s < smax
+    static __device__ __forceinline__ void load(T (&v)[E], const T *__restrict__ base, int ld, int tid,
+                                                bool full, int64_t cmax, int64_t smax)
+    {
+        if (full) {
+#pragma unroll
+            for (int r = 0; r < E; ++r) v[r] = base[c(tid, r) + s(tid, r) * ld];
+        } else {
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int cc = c(tid, r), ss = s(tid, r);
+                v[r] = (cc < cmax && ss < smax) ? base[cc + ss * ld] : (T)0;
+            }
+        }
+    }
+};
+
 // Type-dispatched GEMM: FP64 MFMA for double, split-BF16x3 for float.
 inline evd_status_t gemm_t(hipStream_t s, int opa, int opb, int lower_c, int64_t m, int64_t n, int64_t k, double alpha,
                            const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,

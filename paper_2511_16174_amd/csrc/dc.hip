@@ -299,8 +299,24 @@ __global__ __launch_bounds__(256) void dc_qp_kernel(int64_t n, int t, const doub
     }
 }
 
-// One secular-equation root per thread.
-__global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const double *e, DcArrays a)
+// Sum over the L consecutive lanes of a lane group (L a power of two <= 64).
+__device__ __forceinline__ double group_sum(double v, int L)
+{
+    for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double group_prod(double v, int L)
+{
+    for (int off = L >> 1; off > 0; off >>= 1) v *= __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Secular equation 1 + sigma sum_q z_q^2 / (D_q - lambda) = 0, one root per
+// group of L lanes (each lane sums every L-th pole; the group's lanes hold
+// identical reduced sums, so they take identical decisions).  The root is
+// kept as (origin pole, offset tau) and refined by a bracketed two-pole
+// rational model.
+__global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const double *e, DcArrays a, int L)
 {
     const int64_t i = blockIdx.y;
     int64_t lo, mid, hi;
@@ -308,8 +324,9 @@ __global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const 
     const int *info = a.info + i * 8;
     if (!info[6]) return;
     const int K = info[0];
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= K) return;
+    const int sub = threadIdx.x & (L - 1);
+    const int64_t j = (int64_t)blockIdx.x * (64 / L) + threadIdx.x / L;
+    if (j >= K) return;  // whole groups leave together
     const double sigma = 2.0 * fabs(e[mid - 1]);
     const double *D = a.Dk + lo, *z = a.zk + lo;
 
@@ -318,13 +335,15 @@ __global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const 
     if (j < K - 1) {
         const double gap = D[j + 1] - D[j];
         const double half = 0.5 * gap;
-        double f = 1.0;
-        for (int q = 0; q < K; ++q) f += sigma * z[q] * z[q] / ((D[q] - D[j]) - half);
+        double f = 0.0;
+        for (int q = sub; q < K; q += L) f += sigma * z[q] * z[q] / ((D[q] - D[j]) - half);
+        f = 1.0 + group_sum(f, L);
         if (f > 0.0) { o = (int)j; tlo = 0.0; thi = half; }
         else { o = (int)j + 1; tlo = -half; thi = 0.0; }
     } else {
         double zz = 0.0;
-        for (int q = 0; q < K; ++q) zz += z[q] * z[q];
+        for (int q = sub; q < K; q += L) zz += z[q] * z[q];
+        zz = group_sum(zz, L);
         o = K - 1;
         tlo = 0.0;
         thi = sigma * zz;
@@ -335,19 +354,21 @@ __global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const 
     bool done = false;
     for (int it = 0; it < 200; ++it) {
         double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-        for (int q = 0; q <= j; ++q) {
+        for (int q = sub; q < K; q += L) {
             const double inv = 1.0 / ((D[q] - Do) - tau);
             const double tq = z[q] * z[q] * inv;
-            psi += tq;
-            dpsi += tq * inv;
+            if (q <= j) {
+                psi += tq;
+                dpsi += tq * inv;
+            } else {
+                phi += tq;
+                dphi += tq * inv;
+            }
         }
-        for (int q = (int)j + 1; q < K; ++q) {
-            const double inv = 1.0 / ((D[q] - Do) - tau);
-            const double tq = z[q] * z[q] * inv;
-            phi += tq;
-            dphi += tq * inv;
-        }
-        psi *= sigma; dpsi *= sigma; phi *= sigma; dphi *= sigma;
+        psi = sigma * group_sum(psi, L);
+        dpsi = sigma * group_sum(dpsi, L);
+        phi = sigma * group_sum(phi, L);
+        dphi = sigma * group_sum(dphi, L);
         const double f = 1.0 + psi + phi;
         if (f > 0.0) thi = tau;
         else tlo = tau;
@@ -389,6 +410,7 @@ __global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const 
         last = nt - tau;
         tau = nt;
     }
+    if (sub != 0) return;
     if (!done) atomicMax(a.flag, 1);
     if (tau == 0.0) tau = (o == (int)j) ? 1e-300 : -1e-300;  // never exactly on the pole
     a.org[lo + j] = o;
@@ -398,7 +420,10 @@ __global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const 
 
 // Gu-Eisenstat: zhat_i^2 = (lam_K - D_i)/sigma prod_{j<i} (lam_j - D_i)/(D_j - D_i)
 //                          prod_{i<=j<K-1} (lam_j - D_i)/(D_j+1 - D_i)
-__global__ __launch_bounds__(64) void dc_zhat_kernel(int64_t n, int t, const double *e, DcArrays a)
+// Every factor of the two products lies in (0, 1) by interlacing, so partial
+// products over any subset stay between the full product and 1: the group of
+// L lanes multiplies strided subsets and combines them.
+__global__ __launch_bounds__(64) void dc_zhat_kernel(int64_t n, int t, const double *e, DcArrays a, int L)
 {
     const int64_t i = blockIdx.y;
     int64_t lo, mid, hi;
@@ -406,17 +431,21 @@ __global__ __launch_bounds__(64) void dc_zhat_kernel(int64_t n, int t, const dou
     const int *info = a.info + i * 8;
     if (!info[6]) return;
     const int K = info[0];
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = threadIdx.x & (L - 1);
+    const int64_t q = (int64_t)blockIdx.x * (64 / L) + threadIdx.x / L;
     if (q >= K) return;
     const double sigma = 2.0 * fabs(e[mid - 1]);
     const double *D = a.Dk + lo;
     const int *org = a.org + lo;
     const double *tj = a.tauj + lo;
     const double Dq = D[q];
-    double prod = ((D[org[K - 1]] - Dq) + tj[K - 1]) / sigma;
-    for (int j = 0; j < q; ++j) prod *= ((D[org[j]] - Dq) + tj[j]) / (D[j] - Dq);
-    for (int j = (int)q; j < K - 1; ++j) prod *= ((D[org[j]] - Dq) + tj[j]) / (D[j + 1] - Dq);
-    a.zhat[lo + q] = copysign(sqrt(fmax(prod, 0.0)), a.zk[lo + q]);
+    double prod = 1.0;
+    for (int j = sub; j < K - 1; j += L) {
+        const double den = (j < q) ? (D[j] - Dq) : (D[j + 1] - Dq);
+        prod *= ((D[org[j]] - Dq) + tj[j]) / den;
+    }
+    prod = group_prod(prod, L) * (((D[org[K - 1]] - Dq) + tj[K - 1]) / sigma);
+    if (sub == 0) a.zhat[lo + q] = copysign(sqrt(fmax(prod, 0.0)), a.zk[lo + q]);
 }
 
 // Column j of U: zhat ./ (D - lam_j), normalised; rows placed at gpos.
@@ -670,10 +699,12 @@ evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const
         hipLaunchKernelGGL(dc_prep_kernel, dim3((unsigned)M), dim3(PREP_T), 0, s, n, t, e, (const double *)Z, ldz, a);
         hipLaunchKernelGGL(dc_qp_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M), dim3(256), 0, s, n, t,
                            (const double *)Z, ldz, a);
-        hipLaunchKernelGGL(dc_secular_kernel, dim3((unsigned)evd_ceil_div(smax, 64), (unsigned)M), dim3(64), 0, s, n,
-                           t, e, a);
-        hipLaunchKernelGGL(dc_zhat_kernel, dim3((unsigned)evd_ceil_div(smax, 64), (unsigned)M), dim3(64), 0, s, n, t,
-                           e, a);
+        // lanes per root: enough roots in flight, at least ~32 poles per lane
+        int L = 1;
+        while (L < 64 && (int64_t)L * 64 <= smax) L *= 2;
+        const unsigned gx = (unsigned)evd_ceil_div(smax, 64 / L);
+        hipLaunchKernelGGL(dc_secular_kernel, dim3(gx, (unsigned)M), dim3(64), 0, s, n, t, e, a, L);
+        hipLaunchKernelGGL(dc_zhat_kernel, dim3(gx, (unsigned)M), dim3(64), 0, s, n, t, e, a, L);
         hipLaunchKernelGGL(dc_vec_kernel, dim3((unsigned)smax, (unsigned)M), dim3(64), 0, s, n, t, a);
         EVD_CHECK(gemm_f64_grouped(s, a.probs, (int)(2 * M), smax, smax));
         hipLaunchKernelGGL(dc_rank_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M), dim3(256), 0, s, n,

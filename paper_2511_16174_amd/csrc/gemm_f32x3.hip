@@ -54,48 +54,34 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f32x3_kernel(
     const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
     C += (int64_t)blockIdx.z * split_stride;
 
+    using SAm = TileSlice<float, BM, BK3, NT>;  // contiguous along M
+    using SAk = TileSlice<float, BK3, BM, NT>;  // contiguous along K
+    using SBk = TileSlice<float, BK3, BN, NT>;
+    using SBn = TileSlice<float, BN, BK3, NT>;
+    const int ilda = (int)lda, ildb = (int)ldb;
     float ra[EA], rb[EB];
     int amap = 0;
     auto load_a = [&](int64_t kt) {
+        const int64_t mrem = m - m0, krem = kend - kt;
+        const bool full = mrem >= BM && krem >= BK3;
         if (OPA == OP_N) {
             amap = 0;
-#pragma unroll
-            for (int r = 0; r < EA; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
-                ra[r] = (gi < m && gk < kend) ? A[gi + gk * lda] : 0.0f;
-            }
+            SAm::load(ra, A + m0 + kt * lda, ilda, tid, full, mrem, krem);
         } else if (OPA == OP_T) {
             amap = 1;
-#pragma unroll
-            for (int r = 0; r < EA; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gk = kt + (e % BK3), gi = m0 + (e / BK3);
-                ra[r] = (gi < m && gk < kend) ? A[gk + gi * lda] : 0.0f;
-            }
+            SAk::load(ra, A + kt + m0 * lda, ilda, tid, full, krem, mrem);
         } else {
             if (m0 >= kt + BK3 - 1) {
                 amap = 0;
-#pragma unroll
-                for (int r = 0; r < EA; ++r) {
-                    const int e = tid + r * NT;
-                    const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
-                    ra[r] = (gi < m && gk < kend) ? A[gi + gk * lda] : 0.0f;
-                }
+                SAm::load(ra, A + m0 + kt * lda, ilda, tid, full, mrem, krem);
             } else if (m0 + BM - 1 <= kt) {
                 amap = 1;
-#pragma unroll
-                for (int r = 0; r < EA; ++r) {
-                    const int e = tid + r * NT;
-                    const int64_t gk = kt + (e % BK3), gi = m0 + (e / BK3);
-                    ra[r] = (gi < m && gk < kend) ? A[gk + gi * lda] : 0.0f;
-                }
+                SAk::load(ra, A + kt + m0 * lda, ilda, tid, full, krem, mrem);
             } else {
                 amap = 0;
 #pragma unroll
                 for (int r = 0; r < EA; ++r) {
-                    const int e = tid + r * NT;
-                    const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
+                    const int64_t gi = m0 + SAm::c(tid, r), gk = kt + SAm::s(tid, r);
                     float v = 0.0f;
                     if (gi < m && gk < kend) v = (gi >= gk) ? A[gi + gk * lda] : A[gk + gi * lda];
                     ra[r] = v;
@@ -106,35 +92,22 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f32x3_kernel(
     auto store_a = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < EA; ++r) {
-            const int e = tid + r * NT;
-            const int i = (amap == 0) ? (e % BM) : (e / BK3);
-            const int kk = (amap == 0) ? (e / BM) : (e % BK3);
+            const int i = (amap == 0) ? SAm::c(tid, r) : SAk::s(tid, r);
+            const int kk = (amap == 0) ? SAm::s(tid, r) : SAk::c(tid, r);
             split_bf16(ra[r], &Ah[buf][i][kk], &Al[buf][i][kk]);
         }
     };
     auto load_b = [&](int64_t kt) {
-        if (OPB == OP_N) {
-#pragma unroll
-            for (int r = 0; r < EB; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gk = kt + (e % BK3), gj = n0 + (e / BK3);
-                rb[r] = (gj < n && gk < kend) ? B[gk + gj * ldb] : 0.0f;
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < EB; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gj = n0 + (e % BN), gk = kt + (e / BN);
-                rb[r] = (gj < n && gk < kend) ? B[gj + gk * ldb] : 0.0f;
-            }
-        }
+        const int64_t nrem = n - n0, krem = kend - kt;
+        const bool full = nrem >= BN && krem >= BK3;
+        if (OPB == OP_N) SBk::load(rb, B + kt + n0 * ldb, ildb, tid, full, krem, nrem);
+        else SBn::load(rb, B + n0 + kt * ldb, ildb, tid, full, nrem, krem);
     };
     auto store_b = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < EB; ++r) {
-            const int e = tid + r * NT;
-            const int j = (OPB == OP_N) ? (e / BK3) : (e % BN);
-            const int kk = (OPB == OP_N) ? (e % BK3) : (e / BN);
+            const int j = (OPB == OP_N) ? SBk::s(tid, r) : SBn::c(tid, r);
+            const int kk = (OPB == OP_N) ? SBk::c(tid, r) : SBn::s(tid, r);
             split_bf16(rb[r], &Bh[buf][j][kk], &Bl[buf][j][kk]);
         }
     };

@@ -34,9 +34,12 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
     constexpr int NW = (BM / WM) * (BN / WN);
     constexpr int NT = NW * 64;
     constexpr int TM = WM / 16, TN = WN / 16;
-    constexpr int EA = BM * BK / NT;
-    constexpr int EB = BN * BK / NT;
-    static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile/thread mismatch");
+    using SAm = TileSlice<double, BM, BK, NT>;  // A slice, contiguous along M (A, or the lower triangle read directly)
+    using SAk = TileSlice<double, BK, BM, NT>;  // A slice, contiguous along K (A^T, or the mirrored upper part)
+    using SBk = TileSlice<double, BK, BN, NT>;  // B slice, contiguous along K (B)
+    using SBn = TileSlice<double, BN, BK, NT>;  // B slice, contiguous along N (B^T)
+    constexpr int EA = SAm::E;
+    constexpr int EB = SBk::E;
 
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
@@ -44,51 +47,33 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % (BM / WM), wn = wave / (BM / WM);
+    const int ilda = (int)lda, ildb = (int)ldb;
     (void)k;
 
     double ra[EA], rb[EB];
-    int amap = 0;  // 0: row-fastest mapping, 1: k-fastest mapping (A slice)
+    int amap = 0;  // 0: A slice contiguous along M, 1: along K
 
     auto load_a = [&](int64_t kt) {
+        const int64_t mrem = m - m0, krem = kend - kt;
+        const bool full = mrem >= BM && krem >= BK;
         if (OPA == OP_N) {
             amap = 0;
-#pragma unroll
-            for (int r = 0; r < EA; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
-                ra[r] = (gi < m && gk < kend) ? A[gi + gk * lda] : 0.0;
-            }
+            SAm::load(ra, A + m0 + kt * lda, ilda, tid, full, mrem, krem);
         } else if (OPA == OP_T) {
             amap = 1;
-#pragma unroll
-            for (int r = 0; r < EA; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gk = kt + (e % BK), gi = m0 + (e / BK);
-                ra[r] = (gi < m && gk < kend) ? A[gk + gi * lda] : 0.0;
-            }
+            SAk::load(ra, A + kt + m0 * lda, ilda, tid, full, krem, mrem);
         } else {  // symmetric, lower triangle stored
             if (m0 >= kt + BK - 1) {  // all rows >= all cols: read directly
                 amap = 0;
-#pragma unroll
-                for (int r = 0; r < EA; ++r) {
-                    const int e = tid + r * NT;
-                    const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
-                    ra[r] = (gi < m && gk < kend) ? A[gi + gk * lda] : 0.0;
-                }
+                SAm::load(ra, A + m0 + kt * lda, ilda, tid, full, mrem, krem);
             } else if (m0 + BM - 1 <= kt) {  // all rows <= all cols: mirror
                 amap = 1;
-#pragma unroll
-                for (int r = 0; r < EA; ++r) {
-                    const int e = tid + r * NT;
-                    const int64_t gk = kt + (e % BK), gi = m0 + (e / BK);
-                    ra[r] = (gi < m && gk < kend) ? A[gk + gi * lda] : 0.0;
-                }
+                SAk::load(ra, A + kt + m0 * lda, ilda, tid, full, krem, mrem);
             } else {
                 amap = 0;
 #pragma unroll
                 for (int r = 0; r < EA; ++r) {
-                    const int e = tid + r * NT;
-                    const int64_t gi = m0 + (e % BM), gk = kt + (e / BM);
+                    const int64_t gi = m0 + SAm::c(tid, r), gk = kt + SAm::s(tid, r);
                     double v = 0.0;
                     if (gi < m && gk < kend) v = (gi >= gk) ? A[gi + gk * lda] : A[gk + gi * lda];
                     ra[r] = v;
@@ -99,48 +84,25 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
     auto store_a = [&](int buf) {
         if (amap == 0) {
 #pragma unroll
-            for (int r = 0; r < EA; ++r) {
-                const int e = tid + r * NT;
-                As[buf][e / BM][e % BM] = ra[r];
-            }
+            for (int r = 0; r < EA; ++r) As[buf][SAm::s(tid, r)][SAm::c(tid, r)] = ra[r];
         } else {
 #pragma unroll
-            for (int r = 0; r < EA; ++r) {
-                const int e = tid + r * NT;
-                As[buf][e % BK][e / BK] = ra[r];
-            }
+            for (int r = 0; r < EA; ++r) As[buf][SAk::c(tid, r)][SAk::s(tid, r)] = ra[r];
         }
     };
     auto load_b = [&](int64_t kt) {
-        if (OPB == OP_N) {
-#pragma unroll
-            for (int r = 0; r < EB; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gk = kt + (e % BK), gj = n0 + (e / BK);
-                rb[r] = (gj < n && gk < kend) ? B[gk + gj * ldb] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < EB; ++r) {
-                const int e = tid + r * NT;
-                const int64_t gj = n0 + (e % BN), gk = kt + (e / BN);
-                rb[r] = (gj < n && gk < kend) ? B[gj + gk * ldb] : 0.0;
-            }
-        }
+        const int64_t nrem = n - n0, krem = kend - kt;
+        const bool full = nrem >= BN && krem >= BK;
+        if (OPB == OP_N) SBk::load(rb, B + kt + n0 * ldb, ildb, tid, full, krem, nrem);
+        else SBn::load(rb, B + n0 + kt * ldb, ildb, tid, full, nrem, krem);
     };
     auto store_b = [&](int buf) {
         if (OPB == OP_N) {
 #pragma unroll
-            for (int r = 0; r < EB; ++r) {
-                const int e = tid + r * NT;
-                Bs[buf][e % BK][e / BK] = rb[r];
-            }
+            for (int r = 0; r < EB; ++r) Bs[buf][SBk::c(tid, r)][SBk::s(tid, r)] = rb[r];
         } else {
 #pragma unroll
-            for (int r = 0; r < EB; ++r) {
-                const int e = tid + r * NT;
-                Bs[buf][e / BN][e % BN] = rb[r];
-            }
+            for (int r = 0; r < EB; ++r) Bs[buf][SBn::s(tid, r)][SBn::c(tid, r)] = rb[r];
         }
     };
 
@@ -187,17 +149,22 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
 
     // epilogue: lane holds C(i0 + lane%16, j0 + lane/16 + 4 r), r = 0..3
     const int lr = lane & 15, lq = lane >> 4;
+    const int64_t mw = m0 + wm * WM, nw = n0 + wn * WN;
+    double *Cw = C + mw + nw * ldc;
+    const int ildc = (int)ldc;
+    const bool cfull = (mw + WM <= m) && (nw + WN <= n) && (!LOWER || mw >= nw + WN - 1);
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-        const int64_t gi = m0 + wm * WM + i * 16 + lr;
+        const int li = i * 16 + lr;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gj = n0 + wn * WN + j * 16 + lq + 4 * r;
-                if (gi < m && gj < n && (!LOWER || gi >= gj)) {
+                const int lj = j * 16 + lq + 4 * r;
+                const int64_t gi = mw + li, gj = nw + lj;
+                if (cfull || (gi < m && gj < n && (!LOWER || gi >= gj))) {
+                    double *cp = Cw + (li + lj * ildc);
                     double v = alpha * acc[i][j][r];
-                    double *cp = &C[gi + gj * ldc];
                     if (beta != 0.0) v += beta * (*cp);
                     *cp = v;
                 }
@@ -207,7 +174,7 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
 }
 
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, (OPA == OP_S) ? 1 : 2) void gemm_f64_kernel(
     int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
     int64_t split_stride)
@@ -223,7 +190,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(
 // Grouped product with sizes in device memory: problem blockIdx.z, C = A B
 // (op N, N); tiles outside the problem exit.
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_grouped_kernel(const GemmProblem *probs)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 2) void gemm_f64_grouped_kernel(const GemmProblem *probs)
 {
     const GemmProblem p = probs[blockIdx.z];
     const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;

@@ -2,12 +2,21 @@
 // used by the mixed-precision path (not in the paper): from an approximate
 // eigenvector matrix X of the symmetric A,
 //   R = I - X^T X,  S = X^T A X,  lam_i = s_ii / (1 - r_ii),
-//   delta = 2 (||S - diag(lam)||_2 + ||A||_2 ||R||_2),
+//   delta = 2 (||S - diag(lam)|| + ||A|| ||R||),
 //   E_ij = (s_ij + lam_j r_ij) / (lam_j - lam_i)   if |lam_i - lam_j| > delta
 //          r_ij / 2                                 otherwise,
 //   X <- X + X E.
-// 2-norms are bounded by Frobenius norms (conservative) and ||A||_2 by
-// max |lam_i| (1 + ||R||_F).  All products are FP64 MFMA GEMMs.
+// The norms are Frobenius norms (upper bounds of the 2-norms), ||A|| is
+// bounded by max |lam_i| (1 + ||R||).  Eigenvalues closer than delta form a
+// cluster whose invariant subspace the update refines but whose basis it
+// does not; every cluster of 2..OA_KMAX members is therefore resolved by a
+// Rayleigh-Ritz step in the same sweep: with N = I + R_CC/2 (first-order
+// (X_C^T X_C)^(-1/2)), N S_CC N = V diag(mu) V^T is diagonalised by cyclic
+// Jacobi in FP64 and W_C = N V.  With the block-diagonal W (identity outside
+// the clusters) the sweep continues in the basis Y = X W:
+// S' = W^T S W, R' = I - W^T (I - R) W, lam_C = mu, E' from S', R' as above,
+// and X <- X W (I + E') = X + X (W (I + E') - I).
+// All large products are FP64 MFMA GEMMs.
 #include "common.h"
 
 namespace {
@@ -82,16 +91,248 @@ __global__ void oa_delta_kernel(int nblk, const double *part, double *out)
     out[3] = c;
 }
 
-// E (in place of R): E_ij as in RefSyEv
-__global__ void oa_e_kernel(int64_t n, const double *S, double *R, const double *lam, const double *dl)
+constexpr int OA_KMAX = 64;  // largest cluster resolved by Rayleigh-Ritz
+
+// Clusters along the column order (eigenvalue estimates arrive in ascending
+// order up to errors far below delta): consecutive |lam_i - lam_{i-1}| <=
+// delta.  Clusters of 2..OA_KMAX members are listed (begin, size, offset of
+// their k x k blocks); cid[i] is the list index of column i's cluster or -1.
+// meta: [0] number of listed clusters, [1] largest cluster size.
+__global__ void oa_cluster_kernel(int64_t n, const double *lam, const double *dl, int *cid, int *cl, int *meta)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double delta = dl[0];
+    int ncl = 0, kmax = 1;
+    int64_t off = 0;
+    int64_t b0 = 0;
+    for (int64_t i = 1; i <= n; ++i) {
+        if (i == n || fabs(lam[i] - lam[i - 1]) > delta) {
+            const int k = (int)(i - b0);
+            if (k > kmax) kmax = k;
+            const bool rr = k >= 2 && k <= OA_KMAX;
+            for (int64_t q = b0; q < i; ++q) cid[q] = rr ? ncl : -1;
+            if (rr) {
+                cl[3 * ncl + 0] = (int)b0;
+                cl[3 * ncl + 1] = k;
+                cl[3 * ncl + 2] = (int)off;
+                off += (int64_t)k * k;
+                ++ncl;
+            }
+            b0 = i;
+        }
+    }
+    meta[0] = ncl;
+    meta[1] = kmax;
+}
+
+// Rayleigh-Ritz on one cluster per workgroup: N = I + R_CC/2, M = N S_CC N,
+// cyclic Jacobi M = V diag(mu) V^T; writes W = N V (column-major k x k) and mu.
+__global__ __launch_bounds__(256) void oa_rr_kernel(int64_t n, const double *S, const double *R, const int *cl,
+                                                    const int *meta, double *Wg, double *lam)
+{
+    constexpr int LD = OA_KMAX + 1;
+    __shared__ double A0[OA_KMAX * LD];
+    __shared__ double A1[OA_KMAX * LD];
+    __shared__ double A2[OA_KMAX * LD];
+    __shared__ double rot[2];
+    __shared__ double red[4];
+    const int ncl = meta[0];
+    for (int q = blockIdx.x; q < ncl; q += gridDim.x) {
+    const int64_t b0 = cl[3 * q];
+    const int k = cl[3 * q + 1];
+    const int64_t off = cl[3 * q + 2];
+    const int tid = threadIdx.x;
+    __syncthreads();
+    for (int e = tid; e < k * k; e += 256) {
+        const int a = e % k, c = e / k;
+        A0[a * LD + c] = S[(b0 + a) + (b0 + c) * n];
+        A1[a * LD + c] = ((a == c) ? 1.0 : 0.0) + 0.5 * R[(b0 + a) + (b0 + c) * n];
+    }
+    __syncthreads();
+    // A2 = S N, then A0 = N A2 = N S N
+    for (int e = tid; e < k * k; e += 256) {
+        const int a = e % k, c = e / k;
+        double t = 0.0;
+        for (int p = 0; p < k; ++p) t += A0[a * LD + p] * A1[p * LD + c];
+        A2[a * LD + c] = t;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += 256) {
+        const int a = e % k, c = e / k;
+        double t = 0.0;
+        for (int p = 0; p < k; ++p) t += A1[a * LD + p] * A2[p * LD + c];
+        A0[a * LD + c] = t;
+    }
+    __syncthreads();
+    // symmetrise (rounding) and V = I in A2
+    for (int e = tid; e < k * k; e += 256) {
+        const int a = e % k, c = e / k;
+        if (a > c) {
+            const double m = 0.5 * (A0[a * LD + c] + A0[c * LD + a]);
+            A0[a * LD + c] = m;
+            A0[c * LD + a] = m;
+        }
+        A2[a * LD + c] = (a == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // cyclic Jacobi (Rutishauser's rotation, rotated pair set to zero), until
+    // off(M) <= 1e-16 ||M||_F
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off2 = 0.0, tot = 0.0;
+        for (int e = tid; e < k * k; e += 256) {
+            const int a = e % k, c = e / k;
+            const double m = A0[a * LD + c];
+            tot += m * m;
+            if (a != c) off2 += m * m;
+        }
+        off2 = block_sum(off2, red);
+        tot = block_sum(tot, red);
+        if (off2 <= 1e-32 * tot) break;
+        for (int p = 0; p < k - 1; ++p) {
+            for (int r = p + 1; r < k; ++r) {
+                if (tid == 0) {
+                    const double apq = A0[p * LD + r];
+                    double c = 1.0, sn = 0.0;
+                    if (apq != 0.0) {
+                        const double th = (A0[r * LD + r] - A0[p * LD + p]) / (2.0 * apq);
+                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        sn = t * c;
+                    }
+                    rot[0] = c;
+                    rot[1] = sn;
+                }
+                __syncthreads();
+                const double c = rot[0], sn = rot[1];
+                if (sn != 0.0) {
+                    // rows p, r of M
+                    for (int j = tid; j < k; j += 256) {
+                        const double x = A0[p * LD + j], y = A0[r * LD + j];
+                        A0[p * LD + j] = c * x - sn * y;
+                        A0[r * LD + j] = sn * x + c * y;
+                    }
+                    __syncthreads();
+                    // columns p, r of M and of V
+                    for (int j = tid; j < k; j += 256) {
+                        const double x = A0[j * LD + p], y = A0[j * LD + r];
+                        A0[j * LD + p] = c * x - sn * y;
+                        A0[j * LD + r] = sn * x + c * y;
+                        const double u = A2[j * LD + p], w = A2[j * LD + r];
+                        A2[j * LD + p] = c * u - sn * w;
+                        A2[j * LD + r] = sn * u + c * w;
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        A0[p * LD + r] = 0.0;
+                        A0[r * LD + p] = 0.0;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    for (int e = tid; e < k * k; e += 256) {
+        const int a = e % k, c = e / k;
+        double t = 0.0;
+        for (int p = 0; p < k; ++p) t += A1[a * LD + p] * A2[p * LD + c];
+        Wg[off + e] = t;
+    }
+    for (int a = tid; a < k; a += 256) lam[b0 + a] = A0[a * LD + a];
+    }
+}
+
+// M(i, C) <- M(i, C) W_C for every row i and resolved cluster C (one thread
+// per row; the cluster's k entries of the row stay in registers).
+__global__ __launch_bounds__(256) void oa_colrot_kernel(int64_t n, double *M, const int *cl, const int *meta,
+                                                        const double *Wg)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ncl = meta[0];
+    for (int q = blockIdx.y; q < ncl; q += gridDim.y) {
+        const int64_t b0 = cl[3 * q];
+        const int k = cl[3 * q + 1];
+        const double *W = Wg + cl[3 * q + 2];
+        double *Mr = M + i + b0 * n;
+        double e[OA_KMAX];
+#pragma unroll
+        for (int c = 0; c < OA_KMAX; ++c) e[c] = (c < k) ? Mr[c * n] : 0.0;
+        for (int c = 0; c < k; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int p = 0; p < OA_KMAX; ++p)
+                if (p < k) t += e[p] * W[p + c * k];
+            Mr[c * n] = t;
+        }
+    }
+}
+
+// M(C, j) <- op(W_C) M(C, j) for every column j (op = transpose if trans).
+__global__ __launch_bounds__(256) void oa_rowrot_kernel(int64_t n, double *M, const int *cl, const int *meta,
+                                                        const double *Wg, int trans)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int ncl = meta[0];
+    for (int q = blockIdx.y; q < ncl; q += gridDim.y) {
+        const int64_t b0 = cl[3 * q];
+        const int k = cl[3 * q + 1];
+        const double *W = Wg + cl[3 * q + 2];
+        double *Mc = M + b0 + j * n;
+        double e[OA_KMAX];
+#pragma unroll
+        for (int c = 0; c < OA_KMAX; ++c) e[c] = (c < k) ? Mc[c] : 0.0;
+        for (int a = 0; a < k; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int p = 0; p < OA_KMAX; ++p)
+                if (p < k) t += (trans ? W[p + a * k] : W[a + p * k]) * e[p];
+            Mc[a] = t;
+        }
+    }
+}
+
+// Diagonal blocks after the rotation Y_C = X_C W_C:
+//   R'_CC = I - W^T (I - R_CC) W  (the passes left W^T R_CC W: add I - W^T W);
+//   mode 1 (update): E_CC += W - I.
+__global__ __launch_bounds__(256) void oa_diagfix_kernel(double *M, int64_t n, const int *cl, const int *meta,
+                                                         const double *Wg, int mode)
+{
+    const int ncl = meta[0];
+    for (int q = blockIdx.x; q < ncl; q += gridDim.x) {
+        const int64_t b0 = cl[3 * q];
+        const int k = cl[3 * q + 1];
+        const double *W = Wg + cl[3 * q + 2];
+        for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+            const int a = e % k, c = e / k;
+            double v;
+            if (mode == 0) {
+                double t = 0.0;
+                for (int p = 0; p < k; ++p) t += W[p + a * k] * W[p + c * k];
+                v = ((a == c) ? 1.0 : 0.0) - t;
+            } else {
+                v = W[a + c * k] - ((a == c) ? 1.0 : 0.0);
+            }
+            M[(b0 + a) + (b0 + c) * n] += v;
+        }
+    }
+}
+
+// E_ij as in RefSyEv from the symmetric parts of S and R (the computed
+// products are symmetric only up to rounding; the asymmetric part divided by
+// a small eigenvalue gap would break the orthogonality E_ij + E_ji = r_ij).
+__global__ void oa_e_kernel(int64_t n, const double *S, const double *R, const double *lam, const double *dl,
+                            double *E)
 {
     const double delta = dl[0];
     const int64_t total = n * n;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx % n, j = idx / n;
-        const double r = R[idx];
+        const int64_t tdx = j + i * n;
+        const double r = 0.5 * (R[idx] + R[tdx]);
+        const double sv = 0.5 * (S[idx] + S[tdx]);
         const double d = lam[j] - lam[i];
-        R[idx] = (i != j && fabs(d) > delta) ? (S[idx] + lam[j] * r) / d : 0.5 * r;
+        E[idx] = (i != j && fabs(d) > delta) ? (sv + lam[j] * r) / d : 0.5 * r;
     }
 }
 
@@ -147,33 +388,64 @@ __global__ __launch_bounds__(64) void oa_rayleigh_kernel(int64_t n, const double
     if (threadIdx.x == 0) lam[j] = num / den;
 }
 
+__global__ void oa_meta_stats_kernel(const int *meta, double *stats)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        stats[5] = (double)meta[0];
+        stats[6] = (double)meta[1];
+    }
+}
+
 constexpr int OA_BLOCKS = 1024;
 
 }  // namespace
 
-size_t refine_work_bytes(int64_t n)
+namespace {
+
+struct RefWork {
+    double *R, *AX, *S, *Xn, *part, *Wg;
+    int *cid, *cl, *meta;
+};
+
+size_t ref_layout(int64_t n, char *base, RefWork *w)
 {
     const size_t nn = (size_t)(n > 0 ? n : 1);
-    return 4 * evd_align256(nn * nn * 8) + evd_align256((size_t)OA_BLOCKS * 3 * 8) + 256 * 8 +
-           evd_align256(nn * 8);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += evd_align256(bytes);
+        return (void *)p;
+    };
+    RefWork t;
+    t.R = (double *)take(nn * nn * 8);
+    t.AX = (double *)take(nn * nn * 8);
+    t.S = (double *)take(nn * nn * 8);
+    t.Xn = (double *)take(nn * nn * 8);
+    t.part = (double *)take((size_t)OA_BLOCKS * 3 * 8);
+    t.Wg = (double *)take(nn * OA_KMAX * 8);
+    t.cid = (int *)take(nn * 4);
+    t.cl = (int *)take(nn * 3 * 4);
+    t.meta = (int *)take(64);
+    if (w) *w = t;
+    return off;
 }
+
+}  // namespace
+
+size_t refine_work_bytes(int64_t n) { return ref_layout(n, nullptr, nullptr); }
 
 // One or more RefSyEv sweeps on X (n x n, ldx), A lower-stored FP64.
 // lam (n) receives the refined eigenvalue estimates.  stats (device, 8
-// doubles): [0] delta, [1] ||S - diag(lam)||_F, [2] ||R||_F, [3] max|lam|,
-// [4] residual ||A X - X lam||_F / (n ||A||_F) of the final X, whose
-// Rayleigh quotients are returned in lam.
+// doubles): [0] delta, [1] ||S - diag(lam)||_F, [2] ||R||_F, [3] max|lam| of
+// the last sweep, [4] residual ||A X - X lam||_F / (n ||A||_F) of the final X,
+// whose Rayleigh quotients are returned in lam, [5] clusters resolved by
+// Rayleigh-Ritz and [6] the largest cluster size in the last sweep.
 evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
                         int sweeps, void *work, double *stats)
 {
-    char *base = (char *)work;
-    const size_t nn = (size_t)n;
-    const size_t mat = evd_align256(nn * nn * 8);
-    double *R = (double *)(base);
-    double *AX = (double *)(base + mat);
-    double *S = (double *)(base + 2 * mat);
-    double *Xn = (double *)(base + 3 * mat);
-    double *part = (double *)(base + 4 * mat);
+    RefWork w;
+    ref_layout(n, (char *)work, &w);
+    double *R = w.R, *AX = w.AX, *S = w.S, *Xn = w.Xn, *part = w.part;
     const dim3 g(OA_BLOCKS), t(256);
     for (int sw = 0; sw < sweeps; ++sw) {
         hipLaunchKernelGGL(oa_eye_kernel, g, t, 0, s, n, R, n);
@@ -184,10 +456,33 @@ evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, 
         hipLaunchKernelGGL(oa_norms_kernel, g, t, 0, s, n, (const double *)S, (const double *)R, (const double *)lam,
                            part);
         hipLaunchKernelGGL(oa_delta_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, (const double *)part, stats);
-        hipLaunchKernelGGL(oa_e_kernel, g, t, 0, s, n, (const double *)S, R, (const double *)lam,
-                           (const double *)stats);
+        hipLaunchKernelGGL(oa_cluster_kernel, dim3(1), dim3(64), 0, s, n, (const double *)lam, (const double *)stats,
+                           w.cid, w.cl, w.meta);
+        // Rayleigh-Ritz on the clusters, then S' = Wbd^T S Wbd, R' = I - Wbd^T (I - R) Wbd
+        const unsigned maxcl = (unsigned)(n / 2 < 1024 ? (n / 2 > 0 ? n / 2 : 1) : 1024);
+        const dim3 gr((unsigned)evd_ceil_div(n, 256), maxcl < 64 ? maxcl : 64);
+        hipLaunchKernelGGL(oa_rr_kernel, dim3(maxcl), t, 0, s, n, (const double *)S, (const double *)R,
+                           (const int *)w.cl, (const int *)w.meta, w.Wg, lam);
+        for (int which = 0; which < 2; ++which) {
+            double *M = which ? R : S;
+            hipLaunchKernelGGL(oa_colrot_kernel, gr, t, 0, s, n, M, (const int *)w.cl, (const int *)w.meta,
+                               (const double *)w.Wg);
+            hipLaunchKernelGGL(oa_rowrot_kernel, gr, t, 0, s, n, M, (const int *)w.cl, (const int *)w.meta,
+                               (const double *)w.Wg, 1);
+        }
+        hipLaunchKernelGGL(oa_diagfix_kernel, dim3(maxcl), t, 0, s, R, n, (const int *)w.cl, (const int *)w.meta,
+                           (const double *)w.Wg, 0);
+        // E' in the rotated basis, then F = Wbd (I + E') - I
+        double *E = AX;  // A X is no longer needed
+        hipLaunchKernelGGL(oa_e_kernel, g, t, 0, s, n, (const double *)S, (const double *)R, (const double *)lam,
+                           (const double *)stats, E);
+        hipLaunchKernelGGL(oa_rowrot_kernel, gr, t, 0, s, n, E, (const int *)w.cl, (const int *)w.meta,
+                           (const double *)w.Wg, 0);
+        hipLaunchKernelGGL(oa_diagfix_kernel, dim3(maxcl), t, 0, s, E, n, (const int *)w.cl, (const int *)w.meta,
+                           (const double *)w.Wg, 1);
+        hipLaunchKernelGGL(oa_meta_stats_kernel, dim3(1), dim3(64), 0, s, (const int *)w.meta, stats);
         hipLaunchKernelGGL(oa_copy_kernel, g, t, 0, s, n, (const double *)X, ldx, Xn, n);
-        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, X, ldx, R, n, 1.0, Xn, n, nullptr, 0));
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, X, ldx, E, n, 1.0, Xn, n, nullptr, 0));
         hipLaunchKernelGGL(oa_copy_kernel, g, t, 0, s, n, (const double *)Xn, n, X, ldx);
     }
     // residual of the final X with its Rayleigh quotients

@@ -9,18 +9,23 @@
 // The updated trailing matrix is the next panel's input (Section 2.1.1).
 //
 // Panel QR: the m x b panel is split into row chunks, one workgroup per chunk
-// holding its rows in LDS for the whole factorization.  Column j needs two
-// chip-wide reductions (its norm, then v^T P for the remaining columns plus
-// Y^T v for the T factor); they are separated by grid barriers of a
-// cooperative launch (a counter/generation barrier on device-coherent
-// atomics; the partial sums crossing it use device-coherent accesses too).  The T factor (forward, column-wise:
-// T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T v_j)) is formed at the end by
-// workgroup 0 from the reduced Y^T v products.
+// holding its rows in LDS for the whole factorization.  Column j needs one
+// chip-wide reduction: every workgroup publishes the partial sums
+// h_q = sum_{i > j} P(i, j) P(i, q) for all q (its squared norm for q = j,
+// the dot products with the remaining columns for q > j and with the finished
+// reflectors for q < j), workgroup 0 waits for all of them, reduces them and
+// publishes the sums together with row j; from these every workgroup forms
+// the Householder vector and applies it to its rows.  Flags and data crossing
+// workgroups use device-coherent accesses; flags carry an epoch that grows
+// across columns and panels, so nothing is reset between columns.  The T
+// factor (forward, column-wise: T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T
+// v_j)) is formed at the end by workgroup 0 from the reduced Y^T v products.
 #include "common.h"
 
 namespace {
 
 constexpr int PANEL_THREADS = 256;
+constexpr int PANEL_MAX_WGS = 256;  // workgroups of one panel launch (at most)
 
 template <typename T>
 __global__ void fill_kernel(T *p, int64_t count, T v)
@@ -56,16 +61,20 @@ template <int B, typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, T *P, int64_t lda,
                                                                  T *YZY, int64_t ldy, T *part,
                                                                  T *Sg, T *taus, T *Tout,
-                                                                 T *AB, int64_t ldab, int64_t j0, int *bar)
+                                                                 T *AB, int64_t ldab, int64_t j0, int *flags,
+                                                                 int epoch0)
 {
-    // part layout (G workgroups): [0, G) norms; [G] x0; [G+1, G+1+B) reduced
-    // dots w; then B*G partial dots, column-major by column q: part[D0 + q*G + g].
+    // part[h*B + q]: partial sums of workgroup h; res = part + PANEL_MAX_WGS*B
+    // holds the reduced sums [0, B) and row j of the panel [B, 2B).
+    // flags[h]: epoch of the last column workgroup h has published partials
+    // for; flags[PANEL_MAX_WGS]: epoch of the last reduction of workgroup 0.
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T *smem = (T *)smem_raw;
     const int ldp = chunk + 1;
     T *Ps = smem;                 // Ps[q * ldp + i]: panel column q, local row i
-    __shared__ T wsh[B];
-    __shared__ T red[PANEL_THREADS / 64];
+    __shared__ T hsh[B];
+    __shared__ T topsh[B];
+    __shared__ T coef[B];
     __shared__ T betas[B];
     __shared__ T scal[4];
 
@@ -73,7 +82,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     const int64_t r0 = (int64_t)g * chunk;
     const int rows = (int)((m - r0) < chunk ? (m - r0) : chunk);
     const int nr = (int)(m < B ? m : B);
-    T *partN = part, *partX0 = part + G, *partW = part + G + 1, *partD = part + G + 1 + B;
+    T *res = part + (size_t)PANEL_MAX_WGS * B;
+    int *gen = flags + PANEL_MAX_WGS;
+    T *scr = Ps + B * ldp;        // PANEL_THREADS doubles of scratch after the panel
 
     for (int e = tid; e < rows * B; e += PANEL_THREADS) {
         const int i = e % rows, q = e / rows;
@@ -81,25 +92,62 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     }
     __syncthreads();
 
-    constexpr int TPC = PANEL_THREADS / B;  // threads per column in the dot phase
+    constexpr int TPC = PANEL_THREADS / B;  // threads per column in the dot phases
+    const int cq = tid % B, sub = tid / B;
     for (int j = 0; j < nr; ++j) {
-        // ---- phase 1: partial sum of squares below row j
-        T ss = 0.0;
-        for (int i = tid; i < rows; i += PANEL_THREADS)
-            if (r0 + i > j) { const T x = Ps[j * ldp + i]; ss += x * x; }
-        ss = block_sum(ss, red);
-        if (tid == 0) {
-            st_coh(&partN[g], ss);
-            if (g == 0) st_coh(&partX0[0], Ps[j * ldp + j]);  // row j lives in chunk 0
+        const int E = epoch0 + j + 1;
+        // ---- partial sums h_q = sum over local rows i > j of P(i, j) P(i, q), all q:
+        // q = j is the squared norm below the diagonal, q > j gives v_j^T P(:, q)
+        // and q < j gives Y(:, q)^T v_j (both up to the row-j term and the scale)
+        {
+            T acc = 0.0;
+            for (int i = sub; i < rows; i += TPC)
+                if (r0 + i > j) acc += Ps[j * ldp + i] * Ps[cq * ldp + i];
+            scr[tid] = acc;
+            __syncthreads();
+            if (tid < B) {
+                T s = 0.0;
+#pragma unroll
+                for (int t = 0; t < TPC; ++t) s += scr[tid + t * B];
+                st_coh(&part[(size_t)g * B + tid], s);
+            }
         }
-        grid_barrier_coh(bar, G);
-
-        // ---- phase 2: Householder vector of column j, partial dots
-        T sig = 0.0;
-        for (int h = tid; h < G; h += PANEL_THREADS) sig += ld_coh(&partN[h]);
-        sig = block_sum(sig, red);
+        mem_drain();
+        __syncthreads();
+        if (g != 0) {
+            if (tid == 0) st_coh(&flags[g], E);
+        } else {
+            // workgroup 0 waits for every partial, reduces, and publishes the
+            // sums with row j (which it holds: chunk >= B)
+            if (tid > 0 && tid < G)
+                while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
+            __syncthreads();
+            T s = 0.0;
+            for (int h = sub; h < G; h += TPC) s += ld_coh(&part[(size_t)h * B + cq]);
+            scr[tid] = s;
+            __syncthreads();
+            if (tid < B) {
+                T r = 0.0;
+#pragma unroll
+                for (int t = 0; t < TPC; ++t) r += scr[tid + t * B];
+                st_coh(&res[tid], r);
+                st_coh(&res[B + tid], Ps[tid * ldp + j]);
+            }
+            mem_drain();
+            __syncthreads();
+            if (tid == 0) st_coh(gen, E);
+        }
+        if (g != 0 && tid == 0)
+            while (ld_coh(gen) < E) __builtin_amdgcn_s_sleep(1);
+        __syncthreads();
+        if (tid < B) {
+            hsh[tid] = ld_coh(&res[tid]);
+            topsh[tid] = ld_coh(&res[B + tid]);
+        }
+        __syncthreads();
+        // ---- Householder vector of column j: v = (x - beta e_j) / (x_j - beta)
         if (tid == 0) {
-            const T x0 = ld_coh(&partX0[0]);
+            const T x0 = topsh[j], sig = hsh[j];
             T tau = 0.0, beta = x0, scale = 0.0;
             if (sig != 0.0) {
                 const T nrm = sqrt(x0 * x0 + sig);
@@ -113,52 +161,33 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
         }
         __syncthreads();
         const T tau = scal[0], scale = scal[2];
-        for (int i = tid; i < rows; i += PANEL_THREADS) {
-            const int64_t gi = r0 + i;
-            if (gi > j) Ps[j * ldp + i] *= scale;
-            else if (gi == j) Ps[j * ldp + i] = 1.0;
-        }
-        if (g == 0 && tid == 0) betas[j] = scal[1];
-        __syncthreads();
-        {
-            const int q = tid % B, sub = tid / B;
-            T acc = 0.0;
-            if (q != j)
-                for (int i = sub; i < rows; i += TPC)
-                    if (r0 + i >= j) acc += Ps[j * ldp + i] * Ps[q * ldp + i];
-            Ps[B * ldp + tid] = acc;  // scratch after the panel columns
-            __syncthreads();
-            if (tid < B) {
-                T s = 0.0;
-                for (int t = 0; t < TPC; ++t) s += Ps[B * ldp + tid + t * B];
-                st_coh(&partD[(int64_t)tid * G + g], s);
-            }
-        }
-        grid_barrier_coh(bar, G);
-
-        // ---- phase 3a: workgroup g reduces the partial dots of columns g, g+G, ...
-        for (int q = g; q < B; q += G) {
-            T s = 0.0;
-            for (int h = tid; h < G; h += PANEL_THREADS) s += ld_coh(&partD[(int64_t)q * G + h]);
-            s = block_sum(s, red);
-            if (tid == 0) st_coh(&partW[q], s);
-        }
-        grid_barrier_coh(bar, G);
-
-        // ---- phase 3b: update the remaining columns of the chunk
         if (tid < B) {
-            const T s = ld_coh(&partW[tid]);
-            wsh[tid] = s;
-            if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = s;  // (Y[:, 0:j]^T v_j)
+            const T d = topsh[tid] + scale * hsh[tid];
+            coef[tid] = tau * d;
+            if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = d;  // (Y[:, 0:j]^T v_j)
         }
-        if (g == 0 && tid == 0) taus[j] = tau;
+        if (g == 0 && tid == 0) {
+            taus[j] = tau;
+            betas[j] = scal[1];
+        }
         __syncthreads();
+        // ---- apply H_j to the remaining columns of the chunk, then store v_j
         if (tau != 0.0) {
             const int ncols = B - j - 1;
             for (int e = tid; e < rows * ncols; e += PANEL_THREADS) {
                 const int i = e % rows, q = j + 1 + e / rows;
-                if (r0 + i >= j) Ps[q * ldp + i] -= tau * Ps[j * ldp + i] * wsh[q];
+                const int64_t gi = r0 + i;
+                if (gi >= j) {
+                    const T v = (gi == j) ? (T)1 : scale * Ps[j * ldp + i];
+                    Ps[q * ldp + i] -= v * coef[q];
+                }
             }
+        }
+        __syncthreads();
+        for (int i = tid; i < rows; i += PANEL_THREADS) {
+            const int64_t gi = r0 + i;
+            if (gi > j) Ps[j * ldp + i] *= scale;
+            else if (gi == j) Ps[j * ldp + i] = 1.0;
         }
         __syncthreads();
     }
@@ -202,9 +231,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
 
 template <int B, typename T>
 evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *YZY, int64_t ldy, T *part,
-                          T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar)
+                          T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
 {
-    int maxg = 256;
+    int maxg = PANEL_MAX_WGS;
     if (ctx->panel_wgs > 0 && ctx->panel_wgs < maxg) maxg = (int)ctx->panel_wgs;
     int64_t chunk = evd_ceil_div(m, maxg);
     if (chunk < B) chunk = B;
@@ -217,7 +246,7 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *YZY, i
     if (lds > 150 * 1024) return EVD_ERR_INVALID_ARG;
     int chunk_i = (int)chunk;
     void *args[] = {&m, &chunk_i, &P, (void *)&lda, &YZY, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
-                    (void *)&ldab, (void *)&j0, &bar};
+                    (void *)&ldab, (void *)&j0, &bar, &epoch0};
     hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3(G), dim3(PANEL_THREADS), args,
                                               (unsigned)lds, ctx->stream);
     return e == hipSuccess ? EVD_OK : EVD_ERR_HIP;
@@ -225,16 +254,16 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *YZY, i
 
 template <typename T>
 evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, T *P, int64_t lda, T *YZY, int64_t ldy, T *part,
-                            T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar)
+                            T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
 {
     switch (b) {
-    case 1: return launch_panel<1, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
-    case 2: return launch_panel<2, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
-    case 4: return launch_panel<4, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
-    case 8: return launch_panel<8, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
-    case 16: return launch_panel<16, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
-    case 32: return launch_panel<32, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
-    case 64: return launch_panel<64, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar);
+    case 1: return launch_panel<1, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 2: return launch_panel<2, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 4: return launch_panel<4, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 8: return launch_panel<8, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 16: return launch_panel<16, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 32: return launch_panel<32, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 64: return launch_panel<64, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
     default: return EVD_ERR_INVALID_ARG;
     }
 }
@@ -266,7 +295,7 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     t.YZY = take((size_t)n * 3 * b);
     t.W = take((size_t)n * b);
     t.M = take((size_t)b * b);
-    t.part = take((size_t)256 + 1 + b + (size_t)b * 256 + 64);
+    t.part = take((size_t)PANEL_MAX_WGS * b + 2 * b + 64);
     t.Sg = take((size_t)b * b);
     t.taus = take((size_t)b);
     t.X = nullptr;
@@ -276,7 +305,7 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     if (ws2 > ws) ws = ws2;
     t.gemm_ws = take(ws);
     t.gemm_ws_elems = ws;
-    t.bar = (int *)take(64 / sizeof(T));
+    t.bar = (int *)take((PANEL_MAX_WGS + 64) * sizeof(int) / sizeof(T));
     if (w) *w = t;
     return off;
 }
@@ -297,7 +326,7 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
         hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)(evd_ceil_div(cnt, 256) < 4096 ? evd_ceil_div(cnt, 256) : 4096)),
                            dim3(256), 0, s, AB, cnt, (T)0);
     }
-    hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(64), 0, s, w.bar, (int64_t)2, 0);
+    hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(256), 0, s, w.bar, (int64_t)(PANEL_MAX_WGS + 1), 0);
     const int64_t p = evd_sbr_num_panels(n, b);
     for (int64_t k = 0; k < p; ++k) {
         const int64_t j0 = k * b, i0 = j0 + b, m = n - i0;
@@ -305,7 +334,8 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
         T *A2 = A + i0 + i0 * lda;
         T *Tk = Tf + k * b * b;
         const int64_t ldy = m;
-        EVD_CHECK(panel_dispatch<T>(ctx, b, m, P, lda, w.YZY, ldy, w.part, w.Sg, w.taus, Tk, AB, ldab, j0, w.bar));
+        EVD_CHECK(panel_dispatch<T>(ctx, b, m, P, lda, w.YZY, ldy, w.part, w.Sg, w.taus, Tk, AB, ldab, j0, w.bar,
+                                    (int)(k * (b + 1))));
         T *Y = w.YZY, *Zs = w.YZY + b * ldy;
         // W = Y T
         EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)1, Y, ldy, Tk, b, (T)0, w.W, m, (T *)nullptr, 0));

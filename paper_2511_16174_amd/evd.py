@@ -74,6 +74,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # importing torch first makes this library bind to torch's copy, so the
+    # streams and device memory torch hands out belong to the same runtime
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in PROTOTYPES.items():
         fn = getattr(lib, name)  # AttributeError if a declared symbol is missing

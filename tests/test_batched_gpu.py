@@ -1,0 +1,93 @@
+"""Batched EVD (evd_dsyevd_batched): every matrix of an uneven batch of
+tight-binding Hamiltonians against the oracle; the hipGraph replays agree
+bitwise with a direct (uncaptured) run, with eager work between replays."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.metrics as M
+from paper_2511_16174_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(count, seed, lmin, lmax):
+    Ls, mats = W.tight_binding_batch(count, seed, lmin, lmax)
+    return Ls, mats
+
+
+def run_batched(ctx, mats, graph=1, streams=4, reps=1):
+    import torch
+    ctx.set_param("batch_graph", graph)
+    ctx.set_param("batch_streams", streams)
+    ns = [m.shape[0] for m in mats]
+    pristine = [torch.from_numpy(np.ascontiguousarray(m.T)).cuda() for m in mats]  # column-major
+    As = [p.clone() for p in pristine]
+    Ws = [torch.empty(max(n, 1), dtype=torch.float64, device="cuda") for n in ns]
+    info = torch.zeros(len(mats), dtype=torch.int32, device="cuda")
+    stamps = torch.zeros(2 * len(mats), dtype=torch.int64, device="cuda")
+    wb = ctx.evd_dsyevd_batched_work_size("V", ns, ns)
+    work = torch.empty(wb // 8 + 32, dtype=torch.float64, device="cuda")
+    outs = []
+    for r in range(reps):
+        for a, p in zip(As, pristine):
+            a.copy_(p)                      # eager work between replays
+        torch.cuda.synchronize()
+        ctx.evd_dsyevd_batched("V", "L", ns, As, ns, Ws, work, wb, info, stamps)
+        torch.cuda.synchronize()
+        outs.append(([w[:n].cpu().numpy() for w, n in zip(Ws, ns)],
+                     [a.cpu().numpy().T.copy() for a in As], info.cpu().numpy().copy(),
+                     stamps.cpu().numpy().copy(), ctx.get_param("last_graph_used")))
+    ctx.set_param("batch_graph", 1)
+    return outs
+
+
+def test_batched_tight_binding_vs_oracle():
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    Ls, mats = make_batch(14, seed=7, lmin=3, lmax=13)
+    mats.append(W.gaussian_sym(5, 1))
+    mats.append(np.array([[2.0]]))
+    outs = run_batched(ctx, mats, graph=1, reps=1)
+    ws, Qs, info, stamps, used = outs[0]
+    assert np.all(info == 0)
+    for A, w, Q in zip(mats, ws, Qs):
+        w_ref = oracle.syev(A, jobz="N")
+        assert M.eig_error(w, w_ref) <= 1e-12
+        assert M.residual(A, w, Q) <= 10 and M.orthogonality(Q) <= 10
+    st = stamps.reshape(-1, 2)
+    assert np.all(st[:, 1] >= st[:, 0]) and np.all(st[:, 0] > 0)
+
+
+def test_batched_graph_replays_match_direct_run():
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    Ls, mats = make_batch(10, seed=11, lmin=4, lmax=12)
+    direct = run_batched(ctx, mats, graph=0, reps=1)[0]
+    assert direct[4] == 0
+    replays = run_batched(ctx, mats, graph=1, reps=3)
+    for ws, Qs, info, _, used in replays:
+        assert np.all(info == 0)
+        for a, b in zip(ws, direct[0]):
+            assert np.array_equal(a, b)
+        for a, b in zip(Qs, direct[1]):
+            assert np.array_equal(a, b)
+    print("graph used on replays:", [r[4] for r in replays])
+
+
+def test_autotune_picks_a_candidate_and_keeps_parity():
+    from paper_2511_16174_amd import evd
+    import torch
+    ctx = evd.context(0)
+    n = 700
+    A = W.gaussian_sym(n, seed=5)
+    dA = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    wb = ctx.evd_autotune_work_size("V", n)
+    work = torch.empty(wb // 8 + 32, dtype=torch.float64, device="cuda")
+    b, ms = ctx.evd_autotune("V", n, dA, n, work, wb)
+    assert b in (16, 32, 64) and ms > 0
+    w, Q = evd.eigh(dA, jobz="V")
+    torch.cuda.synchronize()
+    w, Q = w.cpu().numpy(), Q.cpu().numpy()
+    assert M.eig_error(w, oracle.syev(A, jobz="N")) <= 1e-12
+    assert M.residual(A, w, Q) <= 10 and M.orthogonality(Q) <= 10

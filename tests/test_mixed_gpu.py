@@ -63,6 +63,18 @@ def test_mixed_known_spectrum_well_separated():
     assert scaled_res(A, w, Q) <= 1e-13 and scaled_orth(Q) <= 1e-13
 
 
+def test_mixed_clustered_spectrum():
+    """16 clusters of 8 eigenvalues at relative gaps 1e-8: the clusters are
+    resolved by the Rayleigh-Ritz step of the refinement."""
+    n = 512
+    A, lam = W.known_spectrum(n, seed=8, spectrum="clustered", reflectors=16)
+    w, Q, st = run_mixed(A, sweeps=3, b=32)
+    print(f"clustered n={n}: eta={M.eig_error(w, lam):.2e} res={scaled_res(A, w, Q):.2e} "
+          f"orth={scaled_orth(Q):.2e} clusters={st[5]:.0f} kmax={st[6]:.0f}")
+    assert M.eig_error(w, lam) <= 1e-12
+    assert scaled_res(A, w, Q) <= 1e-13 and scaled_orth(Q) <= 1e-13
+
+
 def test_mixed_logspaced_report():
     """Log-spaced |lambda| over [1e-6, 1] with random signs (dense clusters
     near 0): the refinement must not make things worse; the achieved
@@ -74,5 +86,6 @@ def test_mixed_logspaced_report():
     r0, r2 = scaled_res(A, w0, Q0), scaled_res(A, w2, Q2)
     print(f"logspaced n={n}: res0={r0:.2e} res3={r2:.2e} eta={M.eig_error(w2, lam):.2e} "
           f"orth={scaled_orth(Q2):.2e} delta={st[0]:.2e}")
+    print(f"  clusters={st[5]:.0f} kmax={st[6]:.0f}")
     assert r2 <= r0
-    assert M.eig_error(w2, lam) <= 1e-10
+    assert M.eig_error(w2, lam) <= 1e-12
