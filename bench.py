@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--b", type=int, default=64)
     ap.add_argument("--jobz", default="V")
+    ap.add_argument("--order", type=int, default=1,
+                    help="0 = reordered stages (Q_s H.. then Q_sb Q_d), 1 = conventional (Q_s (H.. Q_d))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     args = ap.parse_args()
@@ -79,6 +81,7 @@ def main():
     ctx = evd.context(0)
     ctx.set_param("b", b)
     ctx.set_param("timing", 1)
+    ctx.set_param("order", args.order)
 
     log(f"[bench] generating n={n} on the GPU")
     g = torch.Generator(device=dev)
@@ -116,14 +119,19 @@ def main():
 
     flops3 = 4.0 * n ** 3 / 3.0
     value = flops3 / t / 1e12
-    names = ["sbr", "bc", "dc", "sbr_back", "bc_back", "final_gemm", "total"]
+    if args.order == 0:
+        names = ["sbr", "bc", "dc", "sbr_back", "bc_back", "final_gemm", "total"]
+    else:
+        names = ["sbr", "bc", "dc", "transpose", "bc_back", "sbr_back_left", "total"]
     stages = {names[i]: round(stage_ms[i], 3) for i in range(7)}
 
     # roofline of the dominant single-launch kernel, timed live by the
     # per-stage events on the library's stream: BC-back (one launch, 2 n^3
     # FP64 flops) or the final GEMM (one launch, 2 n^3 flops)
     if args.jobz.upper() == "V":
-        cand = {"bc_back": stage_ms[4], "final_gemm": stage_ms[5]}
+        cand = {"bc_back": stage_ms[4]}
+        if args.order == 0:
+            cand["final_gemm"] = stage_ms[5]
         kname = max(cand, key=cand.get)
         kms = cand[kname]
         achieved = 2.0 * n ** 3 / (kms * 1e-3) / 1e12
@@ -152,7 +160,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"plain FP64 EVD with eigenvectors, n={n}, A=(G+G^T)/(2 sqrt n), G iid N(0,1)",
-                   "n": n, "b": b, "jobz": args.jobz, "uplo": "L", "seed": 3},
+                   "n": n, "b": b, "jobz": args.jobz, "uplo": "L", "seed": 3,
+                   "stage_order": "reordered" if args.order == 0 else "conventional"},
         "stage_ms": stages,
         "roofline": roofline,
     }

@@ -67,6 +67,14 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "order"        0 = reordered stages (paper Section 3.3), 1 = conventional order
  *   "timing"       1 = record per-stage times (host-synchronising; for benchmarks)
  *   "panel_wgs"    cap on the workgroups of one panel-QR launch, 0 = automatic
+ *   "bcback_valu"  1 = apply the bulge-chasing reflectors one by one on the
+ *                  vector ALUs; 0 (default) = in blocks of 32 sweeps on the
+ *                  matrix cores (b = 16, 32, 64)
+ *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 256;
+ *                  a value <= b gives single blocking (one update per panel)
+ *   "last_hip_error" first HIP error code a call met (read; set 0 to clear)
+ *   "capture_error"  HIP error that made the last batched graph capture fall
+ *                  back to a direct run (read only)
  *   "batch_streams", "batch_graph", "last_graph_used"  see evd_dsyevd_batched
  * Unknown keys return EVD_ERR_INVALID_ARG. */
 evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value);

@@ -61,6 +61,7 @@ evd_status_t evd_destroy(evd_ctx_t ctx)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     for (int i = 0; i < ctx->nbstreams; ++i) (void)hipStreamDestroy(ctx->bstreams[i]);
+    if (ctx->cstream) (void)hipStreamDestroy(ctx->cstream);
     for (int i = 0; i < 17; ++i)
         if (ctx->bev[i]) (void)hipEventDestroy(ctx->bev[i]);
     delete ctx;
@@ -83,9 +84,13 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "order")) return &ctx->order;
     if (!strcmp(key, "timing")) return &ctx->timing;
     if (!strcmp(key, "panel_wgs")) return &ctx->panel_wgs;
+    if (!strcmp(key, "sbr_nb")) return &ctx->sbr_nb;
+    if (!strcmp(key, "bcback_valu")) return &ctx->bcback_valu;
     if (!strcmp(key, "batch_streams")) return &ctx->batch_streams;
     if (!strcmp(key, "batch_graph")) return &ctx->batch_graph;
     if (!strcmp(key, "last_graph_used")) return &ctx->last_graph_used;
+    if (!strcmp(key, "last_hip_error")) return &ctx->last_hip_error;
+    if (!strcmp(key, "capture_error")) return &ctx->capture_error;
     return nullptr;
 }
 
@@ -96,6 +101,7 @@ evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value)
     if (!slot) { ctx->last_invalid_arg = 2; return EVD_ERR_INVALID_ARG; }
     if (value < 0) { ctx->last_invalid_arg = 3; return EVD_ERR_INVALID_ARG; }
     *slot = value;
+    if (slot == &ctx->last_hip_error && value == 0) evd_tls_hip_error = 0;
     ctx->last_invalid_arg = 0;
     return EVD_OK;
 }
@@ -105,6 +111,7 @@ evd_status_t evd_get_param(evd_ctx_t ctx, const char *key, int64_t *value)
     if (!ctx || !value) return EVD_ERR_INVALID_ARG;
     int64_t *slot = param_slot(ctx, key);
     if (!slot) { ctx->last_invalid_arg = 2; return EVD_ERR_INVALID_ARG; }
+    if (slot == &ctx->last_hip_error && !ctx->last_hip_error) ctx->last_hip_error = evd_tls_hip_error;
     *value = *slot;
     return EVD_OK;
 }
@@ -158,7 +165,7 @@ evd_status_t evd_dgemm(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_t m
     if (oa == OP_S && ob == OP_T) { /* supported */ }
     if (oa == OP_S && lower_c) { ctx->last_invalid_arg = 4; return EVD_ERR_INVALID_ARG; }
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     return gemm_f64(ctx->stream, oa, ob, lower_c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double *)work,
                     work ? work_bytes / sizeof(double) : 0);
 }

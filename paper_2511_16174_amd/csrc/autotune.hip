@@ -53,7 +53,7 @@ evd_status_t evd_autotune(evd_ctx_t ctx, char jobz, int64_t n, const double *A, 
     ctx->last_invalid_arg = bad;
     if (bad) return bad == 7 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     char *base = (char *)work;
     double *Acopy = (double *)base;
     double *W = (double *)(base + evd_align256((size_t)n * n * sizeof(double)));

@@ -20,6 +20,8 @@
 // k = jj/4 .. jj/4 + b/4 on every lane (out-of-range entries meet zero padding
 // of v).  The four partial dot products of a row are combined with two DPP
 // quad permutations; each partial uses two accumulators to halve the FMA chain.
+#include <utility>
+
 #include "common.h"
 
 namespace {
@@ -27,7 +29,21 @@ namespace {
 constexpr int BCB_G = 64;                     // sweeps per block
 constexpr int VPAD = 4;                       // zero padding on each side of v
 
-template <int B, typename T, int ROWS>
+// Calls f(integral_constant<jj>) for jj = 0..G-1 (descending if REV), so that
+// every window slot index is a compile-time constant.
+template <int G, bool REV, typename F, int... J>
+__device__ __forceinline__ void for_each_reflector(F &&f, std::integer_sequence<int, J...>)
+{
+    if constexpr (REV) (f(std::integral_constant<int, G - 1 - J>{}), ...);
+    else (f(std::integral_constant<int, J>{}), ...);
+}
+
+// REV = false: Q <- Q H_1 ... H_m (generation order, the reordered stages);
+// REV = true:  Q <- Q H_m ... H_1 (reverse order, i.e. rows of Q_d^T for the
+// conventional order).  The reverse order runs the forward schedule
+// backwards: blocks descending, steps ascending, sweeps descending, with the
+// register window sliding right.
+template <int B, typename T, int ROWS, bool REV>
 __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t n, const T *__restrict__ V,
                                                              const T *__restrict__ TAU, T *__restrict__ Q,
                                                              int64_t ldq)
@@ -64,15 +80,37 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
             ts[buf][jj] = (c < nsweeps && s < nsteps) ? TAU[s * n + c] : 0.0;
         }
     };
+    // one reflector of the current group applied to the lane's window slots
+    auto apply = [&](int buf, T(&x)[NW], auto jjc) {
+        constexpr int jj = decltype(jjc)::value;
+        const T tau = ts[buf][jj];
+        const T *v = &vs[buf][jj][VPAD + rho - jj];
+        constexpr int CNT = B / 4 + 1;
+        constexpr int k0 = jj / 4;
+        T d0 = 0.0, d1 = 0.0;
+#pragma clang loop unroll(full)
+        for (int q = 0; q < CNT; q += 2) {
+            const int k = k0 + q;
+            if (k < NW) d0 += x[k] * v[4 * k];
+            if (q + 1 < CNT && k + 1 < NW) d1 += x[k + 1] * v[4 * (k + 1)];
+        }
+        const T w = tau * quad_sum(d0 + d1);
+#pragma clang loop unroll(full)
+        for (int q = 0; q < CNT; ++q) {
+            const int k = k0 + q;
+            if (k < NW) x[k] -= w * v[4 * k];
+        }
+    };
 
     T x[NW];
     T pre[SH];
-    for (int64_t c0 = 0; c0 < nsweeps; c0 += G) {
+    const int64_t c0_first = REV ? ((nsweeps - 1) / G) * G : 0;
+    for (int64_t c0 = c0_first; REV ? (c0 >= 0) : (c0 < nsweeps); c0 += REV ? -G : G) {
         // steps of the first sweep of the block bound the block's steps
         const int64_t rem = n - 1 - (c0 + 1);
         const int64_t S = rem < 0 ? 0 : rem / B + 1;
         if (S == 0) continue;
-        int64_t base = c0 + 1 + (S - 1) * B;
+        int64_t base = REV ? c0 + 1 : c0 + 1 + (S - 1) * B;
         // initial window
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
@@ -80,53 +118,49 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
             x[k] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
         }
         __syncthreads();
-        load_group(0, c0, S - 1);
+        load_group(0, c0, REV ? 0 : S - 1);
         __syncthreads();
         int buf = 0;
-        for (int64_t s = S - 1; s >= 0; --s) {
-            // prefetch the columns entering the window at step s-1, and the
-            // next reflector group
-            if (s > 0) {
+        for (int64_t it = 0; it < S; ++it) {
+            const int64_t s = REV ? it : S - 1 - it;
+            const bool more = it + 1 < S;
+            // prefetch the columns entering the window at the next step, and
+            // the next reflector group
+            if (more) {
 #pragma unroll
                 for (int k = 0; k < SH; ++k) {
-                    const int64_t col = base - B + 4 * k + rho;
+                    const int64_t col = REV ? base + B + 4 * (NW - SH + k) + rho : base - B + 4 * k + rho;
                     pre[k] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
                 }
-                load_group(buf ^ 1, c0, s - 1);
+                load_group(buf ^ 1, c0, REV ? s + 1 : s - 1);
             }
-            // apply the G reflectors of step s, sweeps ascending
-#pragma clang loop unroll(full)
-            for (int jj = 0; jj < G; ++jj) {
-                const T tau = ts[buf][jj];
-                const T *v = &vs[buf][jj][VPAD + rho - jj];
-                constexpr int CNT = B / 4 + 1;
-                const int k0 = jj / 4;
-                T d0 = 0.0, d1 = 0.0;
-#pragma clang loop unroll(full)
-                for (int q = 0; q < CNT; q += 2) {
-                    const int k = k0 + q;
-                    if (k < NW) d0 += x[k] * v[4 * k];
-                    if (q + 1 < CNT && k + 1 < NW) d1 += x[k + 1] * v[4 * (k + 1)];
-                }
-                const T w = tau * quad_sum(d0 + d1);
-#pragma clang loop unroll(full)
-                for (int q = 0; q < CNT; ++q) {
-                    const int k = k0 + q;
-                    if (k < NW) x[k] -= w * v[4 * k];
-                }
-            }
+            // the G reflectors of step s: sweeps ascending (descending for REV)
+            for_each_reflector<G, REV>([&](auto jjc) { apply(buf, x, jjc); }, std::make_integer_sequence<int, G>{});
             // slide: columns leaving the window go back to memory
-            if (s > 0) {
-#pragma clang loop unroll(full)
-                for (int k = NW - SH; k < NW; ++k) {
-                    const int64_t col = base + 4 * k + rho;
-                    if (rowok && col < n) Qr[col * ldq] = x[k];
-                }
-#pragma clang loop unroll(full)
-                for (int k = NW - 1; k >= SH; --k) x[k] = x[k - SH];
+            if (more) {
+                if (REV) {
 #pragma unroll
-                for (int k = 0; k < SH; ++k) x[k] = pre[k];
-                base -= B;
+                    for (int k = 0; k < SH; ++k) {
+                        const int64_t col = base + 4 * k + rho;
+                        if (rowok && col < n) Qr[col * ldq] = x[k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < NW - SH; ++k) x[k] = x[k + SH];
+#pragma unroll
+                    for (int k = 0; k < SH; ++k) x[NW - SH + k] = pre[k];
+                    base += B;
+                } else {
+#pragma unroll
+                    for (int k = NW - SH; k < NW; ++k) {
+                        const int64_t col = base + 4 * k + rho;
+                        if (rowok && col < n) Qr[col * ldq] = x[k];
+                    }
+#pragma unroll
+                    for (int k = NW - 1; k >= SH; --k) x[k] = x[k - SH];
+#pragma unroll
+                    for (int k = 0; k < SH; ++k) x[k] = pre[k];
+                    base -= B;
+                }
             }
             __syncthreads();
             buf ^= 1;
@@ -144,16 +178,18 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
 // generation order, Q read and written in global memory.
 template <typename T>
 __global__ void bcback_simple_kernel(int64_t mrows, int64_t n, int64_t b, const T *__restrict__ V,
-                                     const T *__restrict__ TAU, T *__restrict__ Q, int64_t ldq)
+                                     const T *__restrict__ TAU, T *__restrict__ Q, int64_t ldq, int rev)
 {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= mrows) return;
     const int64_t nsteps = bc_num_steps(n, b);
     T *Qr = Q + row;
-    for (int64_t c = 0; c + 2 < n; ++c) {
-        for (int64_t s = 0; s < nsteps; ++s) {
+    for (int64_t ci = 0; ci + 2 < n; ++ci) {
+        const int64_t c = rev ? n - 3 - ci : ci;
+        for (int64_t si = 0; si < nsteps; ++si) {
+            const int64_t s = rev ? nsteps - 1 - si : si;
             const int64_t r = c + 1 + s * b;
-            if (r >= n) break;
+            if (r >= n) continue;
             const T tau = TAU[s * n + c];
             if (tau == 0.0) continue;
             const int64_t m = (n - r) < b ? (n - r) : b;
@@ -181,20 +217,22 @@ __global__ void eye_kernel(int64_t n, T *Q, int64_t ldq)
 namespace {
 template <typename T>
 evd_status_t bcback_run_t(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const T *V, const T *TAU, T *Q,
-                          int64_t ldq)
+                          int64_t ldq, bool rev)
 {
     hipStream_t s = ctx->stream;
     if (n < 3 || mrows <= 0) return EVD_OK;
-    // 128-row blocks (8 wavefronts, up to 3 per SIMD) once there are enough
-    // rows for every compute unit to get half a block's worth; smaller blocks
-    // for small matrices (each block re-reads every reflector group)
-    const int rows = (mrows >= (int64_t)64 * ctx->num_cus) ? 128 : (mrows >= (int64_t)32 * ctx->num_cus ? 64 : 32);
+    // the largest row block that still gives every compute unit a workgroup
+    // (a row's reflectors are applied in sequence, so rows are the only
+    // parallelism; every block re-reads every reflector group)
+    const int rows = (mrows >= (int64_t)128 * ctx->num_cus) ? 128 : (mrows >= (int64_t)64 * ctx->num_cus ? 64 : 32);
     const dim3 grid((unsigned)evd_ceil_div(mrows, rows));
     const dim3 blk(rows * 4);
-#define EVD_BCB(BB)                                                                                          \
-    if (rows == 128) hipLaunchKernelGGL((bcback_kernel<BB, T, 128>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq); \
-    else if (rows == 64) hipLaunchKernelGGL((bcback_kernel<BB, T, 64>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq); \
-    else hipLaunchKernelGGL((bcback_kernel<BB, T, 32>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq);
+#define EVD_BCB_R(BB, RV)                                                                                        \
+    if (rows == 128) hipLaunchKernelGGL((bcback_kernel<BB, T, 128, RV>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq); \
+    else if (rows == 64) hipLaunchKernelGGL((bcback_kernel<BB, T, 64, RV>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq); \
+    else hipLaunchKernelGGL((bcback_kernel<BB, T, 32, RV>), grid, blk, 0, s, mrows, n, V, TAU, Q, ldq);
+#define EVD_BCB(BB)                                                                                              \
+    if (rev) { EVD_BCB_R(BB, true) } else { EVD_BCB_R(BB, false) }
     switch (b) {
     case 4: EVD_BCB(4) break;
     case 8: EVD_BCB(8) break;
@@ -203,10 +241,11 @@ evd_status_t bcback_run_t(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, co
     case 64: EVD_BCB(64) break;
     default:
         hipLaunchKernelGGL(bcback_simple_kernel<T>, dim3((unsigned)evd_ceil_div(mrows, 256)), dim3(256), 0, s, mrows, n,
-                           b, V, TAU, Q, ldq);
+                           b, V, TAU, Q, ldq, rev ? 1 : 0);
     }
 #undef EVD_BCB
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+#undef EVD_BCB_R
+    return evd_check_last();
 }
 
 }  // namespace
@@ -214,13 +253,20 @@ evd_status_t bcback_run_t(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, co
 evd_status_t bcback_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
                         double *Q, int64_t ldq)
 {
-    return bcback_run_t<double>(ctx, mrows, n, b, V, TAU, Q, ldq);
+    return bcback_run_t<double>(ctx, mrows, n, b, V, TAU, Q, ldq, false);
+}
+
+// Q <- Q H_m ... H_1 (the rows of Q_d^T in the conventional stage order)
+evd_status_t bcback_run_rev(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
+                            double *Q, int64_t ldq)
+{
+    return bcback_run_t<double>(ctx, mrows, n, b, V, TAU, Q, ldq, true);
 }
 
 evd_status_t bcback_run_f32(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const float *V, const float *TAU,
                             float *Q, int64_t ldq)
 {
-    return bcback_run_t<float>(ctx, mrows, n, b, V, TAU, Q, ldq);
+    return bcback_run_t<float>(ctx, mrows, n, b, V, TAU, Q, ldq, false);
 }
 
 // SBR-back.  Q_s = H^(0) H^(1) ... H^(p-1), H^(k) = I - Y_k T_k Y_k^T acting on
@@ -295,11 +341,14 @@ __global__ void orgsb_diag_t_kernel(int64_t nbw, int64_t ldt, int64_t b, int64_t
 
 template <typename T>
 evd_status_t orgsb_run_t(evd_ctx_t ctx, int64_t n, int64_t b, const T *A, int64_t lda, const T *Tf, T *Q,
-                         int64_t ldq, void *work)
+                         int64_t ldq, void *work, bool identity)
 {
+    // identity: Q <- Q_s (accumulated on I, only Q[i0:, i0:] changes per group);
+    // otherwise Q <- Q_s Q for an n x n matrix Q (all columns)
     hipStream_t s = ctx->stream;
-    hipLaunchKernelGGL(eye_kernel<T>, dim3((unsigned)(evd_ceil_div(n * n, 256) < 8192 ? evd_ceil_div(n * n, 256) : 8192)),
-                       dim3(256), 0, s, n, Q, ldq);
+    if (identity)
+        hipLaunchKernelGGL(eye_kernel<T>, dim3((unsigned)(evd_ceil_div(n * n, 256) < 8192 ? evd_ceil_div(n * n, 256) : 8192)),
+                           dim3(256), 0, s, n, Q, ldq);
     OrgsbWork<T> w;
     orgsb_layout<T>(n, b, (char *)work, &w);
     const int64_t p = evd_sbr_num_panels(n, b);
@@ -311,7 +360,8 @@ evd_status_t orgsb_run_t(evd_ctx_t ctx, int64_t n, int64_t b, const T *A, int64_
         const int64_t np = (k0 + gp <= p) ? gp : p - k0;
         const int64_t nbw = np * b;
         const int64_t i0 = k0 * b + b, m = n - i0;
-        T *Qs = Q + i0 + i0 * ldq;
+        const int64_t c0 = identity ? i0 : 0, nc = n - c0;
+        T *Qs = Q + i0 + c0 * ldq;
         const int64_t blocks_y = evd_ceil_div(m * nbw, 256) < 8192 ? evd_ceil_div(m * nbw, 256) : 8192;
         hipLaunchKernelGGL(orgsb_gather_y_kernel<T>, dim3((unsigned)blocks_y), dim3(256), 0, s, m, nbw, b, i0, k0, A,
                            lda, w.Yg);
@@ -329,11 +379,11 @@ evd_status_t orgsb_run_t(evd_ctx_t ctx, int64_t n, int64_t b, const T *A, int64_
             }
         }
         // W1 = Yg^T Q_sub;  W2 = T_g W1;  Q_sub -= Yg W2
-        EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, nbw, m, m, (T)1, w.Yg, m, Qs, ldq, (T)0, w.W1, nb, (T *)nullptr, 0));
-        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, nbw, m, nbw, (T)1, w.Tg, nb, w.W1, nb, (T)0, w.W2, nb, (T *)nullptr, 0));
-        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, m, nbw, (T)-1, w.Yg, m, w.W2, nb, (T)1, Qs, ldq, (T *)nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, nbw, nc, m, (T)1, w.Yg, m, Qs, ldq, (T)0, w.W1, nb, (T *)nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, nbw, nc, nbw, (T)1, w.Tg, nb, w.W1, nb, (T)0, w.W2, nb, (T *)nullptr, 0));
+        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, nc, nbw, (T)-1, w.Yg, m, w.W2, nb, (T)1, Qs, ldq, (T *)nullptr, 0));
     }
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_check_last();
 }
 
 }  // namespace
@@ -348,13 +398,45 @@ size_t orgsb_work_bytes(int64_t n, int64_t b)
 evd_status_t orgsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *Q,
                        int64_t ldq, void *work)
 {
-    return orgsb_run_t<double>(ctx, n, b, A, lda, T, Q, ldq, work);
+    return orgsb_run_t<double>(ctx, n, b, A, lda, T, Q, ldq, work, true);
+}
+
+// C <- Q_s C for an n x n matrix C (the conventional stage order)
+evd_status_t ormsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *C,
+                       int64_t ldc, void *work)
+{
+    return orgsb_run_t<double>(ctx, n, b, A, lda, T, C, ldc, work, false);
+}
+
+// B <- A^T (n x n), 32 x 32 tiles through LDS
+__global__ __launch_bounds__(256) void transpose_kernel(int64_t n, const double *__restrict__ A, int64_t lda,
+                                                        double *__restrict__ B, int64_t ldb)
+{
+    __shared__ double tile[32][33];
+    const int64_t bi = (int64_t)blockIdx.x * 32, bj = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bi + tx, j = bj + r;
+        if (i < n && j < n) tile[r][tx] = A[i + j * lda];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bj + tx, j = bi + r;
+        if (i < n && j < n) B[i + j * ldb] = tile[tx][r];
+    }
+}
+
+evd_status_t transpose_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *B, int64_t ldb)
+{
+    const dim3 grid((unsigned)evd_ceil_div(n, 32), (unsigned)evd_ceil_div(n, 32));
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, n, A, lda, B, ldb);
+    return evd_check_last();
 }
 
 evd_status_t orgsb_run_f32(evd_ctx_t ctx, int64_t n, int64_t b, const float *A, int64_t lda, const float *T, float *Q,
                            int64_t ldq, void *work)
 {
-    return orgsb_run_t<float>(ctx, n, b, A, lda, T, Q, ldq, work);
+    return orgsb_run_t<float>(ctx, n, b, A, lda, T, Q, ldq, work, true);
 }
 
 extern "C" {
@@ -386,7 +468,7 @@ evd_status_t evd_dorgsb(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, in
     if (bad) return bad == 10 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     return orgsb_run(ctx, n, b, A, lda, T, Q, ldq, work);
 }
 
@@ -406,7 +488,7 @@ evd_status_t evd_dbcback(evd_ctx_t ctx, int64_t m_rows, int64_t n, int64_t b, co
     if (bad) return EVD_ERR_INVALID_ARG;
     if (n < 3 || m_rows == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     return bcback_run(ctx, m_rows, n, b, V, TAU, Q, ldq);
 }
 

@@ -119,16 +119,15 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
     if (bad) return bad == 10 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (batch == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
 
     const int ns = num_streams(ctx);
     while (ctx->nbstreams < ns) {
-        if (hipStreamCreateWithFlags(&ctx->bstreams[ctx->nbstreams], hipStreamNonBlocking) != hipSuccess)
-            return EVD_ERR_HIP;
+        EVD_CHECK(evd_hip(ctx, hipStreamCreateWithFlags(&ctx->bstreams[ctx->nbstreams], hipStreamNonBlocking)));
         ctx->nbstreams++;
     }
     for (int i = 0; i <= ns; ++i)
-        if (!ctx->bev[i] && hipEventCreateWithFlags(&ctx->bev[i], hipEventDisableTiming) != hipSuccess) return EVD_ERR_HIP;
+        if (!ctx->bev[i]) EVD_CHECK(evd_hip(ctx, hipEventCreateWithFlags(&ctx->bev[i], hipEventDisableTiming)));
 
     // key of the captured graph: everything the launch sequence depends on
     uint64_t key = mix(0x1234, (uint64_t)batch);
@@ -148,20 +147,20 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
     }
     if (ctx->batch_graph && ctx->gexec && ctx->gkey == key) {
         ctx->last_graph_used = 1;
-        return hipGraphLaunch(ctx->gexec, ctx->stream) == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+        return evd_hip(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
     }
 
     hipStream_t main = ctx->stream;
     const int64_t saved_bc = ctx->bc_waves, saved_pw = ctx->panel_wgs, saved_t = ctx->timing;
     const int64_t cap = (ctx->num_cus / ns) > 1 ? (ctx->num_cus / ns) : 1;
-    auto enqueue = [&]() -> evd_status_t {
+    // fork from `origin` onto the internal streams, join back into it
+    auto enqueue = [&](hipStream_t origin) -> evd_status_t {
         ctx->bc_waves = (saved_bc > 0 && saved_bc < cap) ? saved_bc : cap;
         ctx->panel_wgs = (saved_pw > 0 && saved_pw < cap) ? saved_pw : cap;
         ctx->timing = 0;
         evd_status_t st = EVD_OK;
-        if (hipEventRecord(ctx->bev[ns], main) != hipSuccess) st = EVD_ERR_HIP;
-        for (int k = 0; st == EVD_OK && k < ns; ++k)
-            if (hipStreamWaitEvent(ctx->bstreams[k], ctx->bev[ns], 0) != hipSuccess) st = EVD_ERR_HIP;
+        st = evd_hip(ctx, hipEventRecord(ctx->bev[ns], origin));
+        for (int k = 0; st == EVD_OK && k < ns; ++k) st = evd_hip(ctx, hipStreamWaitEvent(ctx->bstreams[k], ctx->bev[ns], 0));
         for (int idx = 0; st == EVD_OK && idx < batch; ++idx) {
             const int i = p.order[idx];
             const int k = p.stream_of[i];
@@ -173,8 +172,8 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
         }
         ctx->stream = main;
         for (int k = 0; st == EVD_OK && k < ns; ++k) {
-            if (hipEventRecord(ctx->bev[k], ctx->bstreams[k]) != hipSuccess) st = EVD_ERR_HIP;
-            else if (hipStreamWaitEvent(main, ctx->bev[k], 0) != hipSuccess) st = EVD_ERR_HIP;
+            st = evd_hip(ctx, hipEventRecord(ctx->bev[k], ctx->bstreams[k]));
+            if (st == EVD_OK) st = evd_hip(ctx, hipStreamWaitEvent(origin, ctx->bev[k], 0));
         }
         ctx->bc_waves = saved_bc;
         ctx->panel_wgs = saved_pw;
@@ -183,13 +182,21 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
     };
 
     ctx->last_graph_used = 0;
+    ctx->capture_error = 0;
     if (ctx->batch_graph) {
-        // capture; if anything in the sequence cannot be captured, fall back to
-        // running it directly (reported through the "last_graph_used" parameter)
+        // capture on an internal stream (the caller's may be the null stream,
+        // which cannot be captured) and launch the graph on the caller's
+        // stream; if anything in the sequence cannot be captured, fall back to
+        // running it directly (reported through "last_graph_used")
+        if (!ctx->cstream) EVD_CHECK(evd_hip(ctx, hipStreamCreateWithFlags(&ctx->cstream, hipStreamNonBlocking)));
         hipGraph_t graph = nullptr;
-        if (hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            evd_status_t st = enqueue();
-            hipError_t ec = hipStreamEndCapture(main, &graph);
+        const hipError_t eb = hipStreamBeginCapture(ctx->cstream, hipStreamCaptureModeThreadLocal);
+        if (eb != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->capture_error = (int64_t)eb;
+        } else {
+            evd_status_t st = enqueue(ctx->cstream);
+            hipError_t ec = hipStreamEndCapture(ctx->cstream, &graph);
             if (st == EVD_OK && ec == hipSuccess && graph) {
                 hipGraphExec_t exec = nullptr;
                 if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
@@ -198,14 +205,17 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
                     ctx->gkey = key;
                     (void)hipGraphDestroy(graph);
                     ctx->last_graph_used = 1;
-                    return hipGraphLaunch(ctx->gexec, main) == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+                    return evd_hip(ctx, hipGraphLaunch(ctx->gexec, main));
                 }
             }
             if (graph) (void)hipGraphDestroy(graph);
             (void)hipGetLastError();
+            ctx->capture_error = ctx->last_hip_error ? ctx->last_hip_error : (int64_t)(ec != hipSuccess ? ec : -1);
+            ctx->last_hip_error = 0;
+            evd_tls_hip_error = 0;
         }
     }
-    return enqueue();
+    return enqueue(main);
 }
 
 }  // extern "C"

@@ -256,7 +256,7 @@ evd_status_t bc_launch(evd_ctx_t ctx, int64_t n, T *AB, int64_t ldab, T *V, T *T
 {
     int per_cu = 0;
     constexpr int NT = bc_threads(B);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc_kernel<B, T>, NT, 0) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc_kernel<B, T>, NT, 0)));
     if (per_cu < 1) per_cu = 1;
     int64_t P = (int64_t)per_cu * ctx->num_cus;
     if (ctx->bc_waves > 0 && ctx->bc_waves < P) P = ctx->bc_waves;
@@ -266,7 +266,7 @@ evd_status_t bc_launch(evd_ctx_t ctx, int64_t n, T *AB, int64_t ldab, T *V, T *T
     void *args[] = {(void *)&n, &AB, (void *)&ldab, &V, &TAU, &prog, &store_v};
     hipError_t e = hipLaunchCooperativeKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args, 0,
                                               ctx->stream);
-    return e == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_hip(ctx, e);
 }
 
 }  // namespace
@@ -302,7 +302,7 @@ evd_status_t bc_run_t(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, T *AB, int
     }
     hipLaunchKernelGGL(bc_extract_kernel<T>, dim3((unsigned)(evd_ceil_div(n, 256) < 1024 ? evd_ceil_div(n, 256) : 1024)),
                        dim3(256), 0, s, n, (const T *)AB, ldab, d, e);
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_check_last();
 }
 
 }  // namespace
@@ -352,7 +352,7 @@ evd_status_t evd_dsb2st(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *
     if (bad) return bad == 12 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     return bc_run(ctx, jobz, n, b, AB, ldab, d, e, V, TAU, (int *)work);
 }
 

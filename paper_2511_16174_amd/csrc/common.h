@@ -161,16 +161,43 @@ struct evd_ctx_s {
     // autotuned band width per size bucket (bucket = floor(log2 n)), 0 = none
     int64_t tuned_b[64];
     int64_t panel_wgs;        // cap on panel-QR workgroups (0 = automatic)
+    int64_t sbr_nb;           // SBR outer block in columns (0 = 256; <= b: single blocking)
+    int64_t bcback_valu;      // 1 = reflector-by-reflector BC-back on the vector ALUs (0 = blocked MFMA)
     int64_t batch_streams;    // streams used by the batched driver (0 = 4)
     int64_t batch_graph;      // 1 = capture the batched launch sequence in a hipGraph
     int64_t last_graph_used;  // 1 if the last batched call ran from a graph
+    int64_t last_hip_error;   // first HIP error code seen by a call (0 = none; cleared by evd_set_param)
+    int64_t capture_error;    // HIP error that made the last graph capture fall back (0 = none)
     // batched driver state
     hipStream_t bstreams[16];
+    hipStream_t cstream;      // origin stream of the batched graph capture
     hipEvent_t bev[17];
     int nbstreams;
     hipGraphExec_t gexec;
     uint64_t gkey;
 };
+
+// First failing HIP status seen on this host thread (internal helpers without
+// a context record here; the context reports it through "last_hip_error").
+inline thread_local int64_t evd_tls_hip_error = 0;
+
+inline evd_status_t evd_hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return EVD_OK;
+    if (!evd_tls_hip_error) evd_tls_hip_error = (int64_t)e;
+    return EVD_ERR_HIP;
+}
+
+// Launch errors of the kernels enqueued so far (consumes hipGetLastError).
+inline evd_status_t evd_check_last() { return evd_hip_status(hipGetLastError()); }
+
+// Record the first failing HIP status of a call in the context.
+inline evd_status_t evd_hip(evd_ctx_s *ctx, hipError_t e)
+{
+    if (e == hipSuccess) return EVD_OK;
+    if (!ctx->last_hip_error) ctx->last_hip_error = (int64_t)e;
+    return evd_hip_status(e);
+}
 
 // Band width used by the drivers: explicit parameter, else the autotuned
 // value for n's size bucket, else the default (32 up to n = 4096, then 64),

@@ -686,7 +686,7 @@ evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const
         hipLaunchKernelGGL(dc_bisect_kernel, dim3((unsigned)evd_ceil_div(n, 64)), dim3(64), 0, s, n, d, e, W,
                            (const double *)g);
         if (info) hipLaunchKernelGGL(dc_zero_int, dim3(1), dim3(64), 0, s, (int *)info, (int64_t)1);
-        return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+        return evd_check_last();
     }
     DcArrays a;
     dc_layout(n, (char *)work, &a);
@@ -711,11 +711,11 @@ evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const
                            t, a);
         hipLaunchKernelGGL(dc_scatter_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M), dim3(256), 0, s,
                            n, t, Z, ldz, a);
-        if (hipGetLastError() != hipSuccess) return EVD_ERR_HIP;
+        EVD_CHECK(evd_check_last());
     }
     hipLaunchKernelGGL(dc_copy_kernel, grid1(n), dim3(256), 0, s, n, (const double *)a.Dw, W);
     if (info) hipLaunchKernelGGL(dc_info_kernel, dim3(1), dim3(64), 0, s, (const int *)a.flag, info);
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_check_last();
 }
 
 extern "C" {
@@ -748,7 +748,7 @@ evd_status_t evd_dstedc(evd_ctx_t ctx, char compz, int64_t n, const double *d, c
     if (bad) return bad == 10 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     return dc_run(ctx, vec ? 'I' : 'N', n, d, e, W, Z, ldz, work, info);
 }
 

@@ -7,6 +7,9 @@
 //   SBR-back (Q_s on the identity)           stage 4a  (Section 2.1.2)
 //   BC-back  (Q_sb = Q_s H_1 ... H_m)        stage 4b  (Section 4.3)
 //   final GEMM Q = Q_sb Q_d                  stage 5   (Section 3.3)
+// or, with the "order" parameter set to 1, the conventional order
+// Q = Q_s (H_1 ... H_m Q_d), which needs no final GEMM (fewer flops when the
+// stages run one after the other on one device).
 // Eigenvalues only: SBR -> BC (no reflectors kept) -> bisection.
 #include "common.h"
 
@@ -23,13 +26,21 @@ evd_status_t orgsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int
 size_t orgsb_work_bytes(int64_t n, int64_t b);
 evd_status_t bcback_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
                         double *Q, int64_t ldq);
+evd_status_t bcback_run_rev(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
+                            double *Q, int64_t ldq);
+evd_status_t ormsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *C,
+                       int64_t ldc, void *work);
+evd_status_t transpose_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *B, int64_t ldb);
+size_t bcback_mfma_t_elems(int64_t n, int64_t b);
+evd_status_t bcback_mfma_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
+                             double *Q, int64_t ldq, double *Tg, bool rev);
 
 namespace {
 
 int64_t choose_b(evd_ctx_t ctx, int64_t n) { return evd_choose_b(ctx, n); }
 
 struct EvdWork {
-    double *AB, *T, *d, *e, *V, *TAU, *Qs, *Qd;
+    double *AB, *T, *d, *e, *V, *TAU, *Qs, *Qd, *Tg;
     int *prog;
     void *sbr, *dc, *orgsb;
     int64_t b, ldab;
@@ -62,13 +73,22 @@ size_t evd_layout(int64_t n, int64_t b, bool vec, char *base, EvdWork *w)
         t.Qd = (double *)take(nn * nn * 8);
         t.dc = take(dc_work_bytes('I', n));
         t.orgsb = take(orgsb_work_bytes(n, b));
+        const size_t tge = bcback_mfma_t_elems(n, b);
+        t.Tg = tge ? (double *)take(tge * 8) : nullptr;
     } else {
-        t.V = t.TAU = t.Qs = t.Qd = nullptr;
+        t.V = t.TAU = t.Qs = t.Qd = t.Tg = nullptr;
         t.dc = take(dc_work_bytes('N', n));
         t.orgsb = nullptr;
     }
     if (w) *w = t;
     return off;
+}
+
+__global__ void copy_kernel(int64_t n, const double *src, int64_t lds, double *dst, int64_t ldd)
+{
+    const int64_t total = n * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x)
+        dst[(idx % n) + (idx / n) * ldd] = src[(idx % n) + (idx / n) * lds];
 }
 
 __global__ void trivial_kernel(int64_t n, double *A, double *W, int vec, int32_t *info)
@@ -83,6 +103,17 @@ __global__ void trivial_kernel(int64_t n, double *A, double *W, int vec, int32_t
 }
 
 }  // namespace
+
+// Workspace of evd_dsyevd(jobz = 'V') for any band width the drivers may pick.
+size_t dsyevd_work_bytes_any_b(int64_t n)
+{
+    size_t m = 0;
+    for (int64_t b = 1; b <= 64; b *= 2) {
+        const size_t w = evd_layout(n, b, true, nullptr, nullptr);
+        if (w > m) m = w;
+    }
+    return m;
+}
 
 extern "C" {
 
@@ -120,13 +151,13 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
     if (bad) return bad == 9 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     hipStream_t s = ctx->stream;
     const bool timing = ctx->timing != 0;
     for (int i = 0; i < 8; ++i) ctx->stage_ms[i] = 0.0f;
     if (n == 1) {
         hipLaunchKernelGGL(trivial_kernel, dim3(1), dim3(64), 0, s, n, A, W, vec ? 1 : 0, info);
-        return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+        return evd_hip(ctx, hipGetLastError());
     }
     EvdWork w;
     evd_layout(n, b, vec, (char *)work, &w);
@@ -143,12 +174,33 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
     } else {
         EVD_CHECK(dc_run(ctx, 'I', n, w.d, w.e, W, w.Qd, n, w.dc, info));
         mark(3);
-        EVD_CHECK(orgsb_run(ctx, n, b, A, lda, w.T, w.Qs, n, w.orgsb));
-        mark(4);
-        EVD_CHECK(bcback_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n));
-        mark(5);
-        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, w.Qs, n, w.Qd, n, 0.0, A, lda, nullptr, 0));
-        mark(6);
+        if (ctx->order == 0) {
+            // reordered stages (Section 3.3): Q_sb = Q_s H_1 ... H_m, then Q = Q_sb Q_d
+            EVD_CHECK(orgsb_run(ctx, n, b, A, lda, w.T, w.Qs, n, w.orgsb));
+            mark(4);
+            if (w.Tg && ctx->bcback_valu == 0)
+                EVD_CHECK(bcback_mfma_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n, w.Tg, false));
+            else
+                EVD_CHECK(bcback_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n));
+            mark(5);
+            EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, w.Qs, n, w.Qd, n, 0.0, A, lda, nullptr, 0));
+            mark(6);
+        } else {
+            // conventional order: Z = H_1 ... H_m Q_d as rows of Z^T = Q_d^T H_m ... H_1,
+            // then Q = Q_s Z (the panel reflectors still live in A's panel columns)
+            // stage times: [3] transpose, [4] BC-back alone, [5] transpose + SBR-back + copy
+            EVD_CHECK(transpose_run(s, n, w.Qd, n, w.Qs, n));
+            mark(4);
+            if (w.Tg && ctx->bcback_valu == 0)
+                EVD_CHECK(bcback_mfma_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n, w.Tg, true));
+            else
+                EVD_CHECK(bcback_run_rev(ctx, n, n, b, w.V, w.TAU, w.Qs, n));
+            mark(5);
+            EVD_CHECK(transpose_run(s, n, w.Qs, n, w.Qd, n));
+            EVD_CHECK(ormsb_run(ctx, n, b, A, lda, w.T, w.Qd, n, w.orgsb));
+            hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, s, n, (const double *)w.Qd, n, A, lda);
+            mark(6);
+        }
     }
     if (timing) {
         if (hipEventSynchronize(ctx->ev[vec ? 6 : 3]) != hipSuccess) return EVD_ERR_HIP;
@@ -159,7 +211,7 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
         }
         if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[last]) == hipSuccess) ctx->stage_ms[6] = ms;
     }
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_hip(ctx, hipGetLastError());
 }
 
 }  // extern "C"

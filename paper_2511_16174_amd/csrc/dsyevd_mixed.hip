@@ -24,7 +24,7 @@ size_t orgsb_work_bytes(int64_t n, int64_t b);
 evd_status_t bcback_run_f32(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const float *V, const float *TAU,
                             float *Q, int64_t ldq);
 size_t refine_work_bytes(int64_t n);
-evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
+evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
                         int sweeps, void *work, double *stats);
 
 namespace {
@@ -177,7 +177,7 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     if (bad) return bad == 10 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     hipStream_t s = ctx->stream;
     if (n < 3) {
         // tiny problems: the FP64 driver's workspace fits in ours
@@ -211,7 +211,7 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     EVD_CHECK(gemm_f32x3(s, OP_N, OP_N, 0, n, n, n, 1.0f, w.Qs, n, w.Qd32, n, 0.0f, w.X32, n, nullptr, 0));
     hipLaunchKernelGGL(mx_up_kernel, g, t, 0, s, nn, (const float *)w.X32, w.Xd);
     mark(6);
-    EVD_CHECK(refine_run(s, n, A, lda, w.Xd, n, w.lam, sweeps, w.ref, w.stats));
+    EVD_CHECK(refine_run(ctx, n, A, lda, w.Xd, n, w.lam, sweeps, w.ref, w.stats));
     hipLaunchKernelGGL(mx_rank_kernel, dim3((unsigned)evd_ceil_div(n, 256)), t, 0, s, n, (const double *)w.lam, w.pos);
     hipLaunchKernelGGL(mx_scatter_kernel, g, t, 0, s, n, (const double *)w.Xd, (const double *)w.lam,
                        (const int *)w.pos, A, lda, W);
@@ -224,7 +224,7 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
             if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess) ctx->stage_ms[i] = ms;
         if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[7]) == hipSuccess) ctx->stage_ms[7] = ms;
     }
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_check_last();
 }
 
 }  // extern "C"

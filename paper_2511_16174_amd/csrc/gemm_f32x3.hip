@@ -267,7 +267,7 @@ evd_status_t gemm_f32x3(hipStream_t s, int opa, int opb, int lower_c, int64_t m,
         if (beta == 1.0f) return EVD_OK;
         hipLaunchKernelGGL(splitk_reduce_f32_kernel, dim3(1024), dim3(256), 0, s, m, n, 0, (const float *)nullptr,
                            (int64_t)0, 0.0f, beta, C, ldc, lower_c);
-        return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+        return evd_check_last();
     }
     Plan3 p = plan3(m, n, k, ws ? ws_elems : 0);
     const int lower = lower_c ? 1 : 0;
@@ -294,13 +294,13 @@ evd_status_t gemm_f32x3(hipStream_t s, int opa, int opb, int lower_c, int64_t m,
     else
         launch_ops3<64, 64, 32, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
                                     sstride);
-    if (hipGetLastError() != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_check_last());
     if (p.splits > 1) {
         int64_t blocks = evd_ceil_div(m * n, 256);
         if (blocks > 65535) blocks = 65535;
         hipLaunchKernelGGL(splitk_reduce_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, n, p.splits, ws,
                            sstride, alpha, beta, C, ldc, lower);
-        if (hipGetLastError() != hipSuccess) return EVD_ERR_HIP;
+        EVD_CHECK(evd_check_last());
     }
     return EVD_OK;
 }
@@ -335,7 +335,7 @@ evd_status_t evd_sgemm_x3(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_
     ctx->last_invalid_arg = bad;
     if (bad) return EVD_ERR_INVALID_ARG;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     return gemm_f32x3(ctx->stream, oa, ob, lower_c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (float *)work,
                       work ? work_bytes / sizeof(float) : 0);
 }

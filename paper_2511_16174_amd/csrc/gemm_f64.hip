@@ -295,7 +295,7 @@ evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob
         dim3 grid((unsigned)evd_ceil_div(max_m, 64), (unsigned)evd_ceil_div(max_n, 64), (unsigned)nprob);
         hipLaunchKernelGGL((gemm_f64_grouped_kernel<64, 64, 32, 32>), grid, dim3(256), 0, s, probs);
     }
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_check_last();
 }
 
 size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k)
@@ -316,7 +316,7 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
                                                           ? (unsigned)evd_ceil_div(m * n, 256 * 4) : 65535u),
                            dim3(256), 0, s, m, n, 0, (const double *)nullptr, (int64_t)0, 0.0, beta, C, ldc,
                            lower_c);
-        return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+        return evd_check_last();
     }
     GemmPlan p = plan_gemm(m, n, k, ws ? ws_elems : 0);
     const int lower = lower_c ? 1 : 0;
@@ -343,13 +343,13 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
     else
         launch_ops<64, 64, 32, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
                                    sstride);
-    if (hipGetLastError() != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_check_last());
     if (p.splits > 1) {
         int64_t blocks = evd_ceil_div(m * n, 256);
         if (blocks > 65535) blocks = 65535;
         hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, n, p.splits, ws,
                            sstride, alpha, beta, C, ldc, lower);
-        if (hipGetLastError() != hipSuccess) return EVD_ERR_HIP;
+        EVD_CHECK(evd_check_last());
     }
     return EVD_OK;
 }

@@ -17,6 +17,8 @@
 // S' = W^T S W, R' = I - W^T (I - R) W, lam_C = mu, E' from S', R' as above,
 // and X <- X W (I + E') = X + X (W (I + E') - I).
 // All large products are FP64 MFMA GEMMs.
+#include <vector>
+
 #include "common.h"
 
 namespace {
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(256) void oa_norms_kernel(int64_t n, const double *
 }
 
 // delta from the per-block partials (one thread; fixed order -> deterministic)
-__global__ void oa_delta_kernel(int nblk, const double *part, double *out)
+__global__ void oa_delta_kernel(int nblk, int64_t n, const double *part, double *out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double a = 0.0, b = 0.0, c = 0.0;
@@ -85,7 +87,10 @@ __global__ void oa_delta_kernel(int nblk, const double *part, double *out)
         c = fmax(c, part[q * 3 + 2]);
     }
     const double rn = sqrt(b);
-    out[0] = 2.0 * (sqrt(a) + c * (1.0 + rn) * rn);  // delta
+    // at least sqrt(n eps) max|lam|: below that gap the Newton-type update
+    // divides the rounding noise of S by the gap and loses orthogonality
+    const double floor_ = sqrt((double)n * 2.220446049250313e-16) * c;
+    out[0] = fmax(2.0 * (sqrt(a) + c * (1.0 + rn) * rn), floor_);  // delta
     out[1] = sqrt(a);
     out[2] = rn;
     out[3] = c;
@@ -96,13 +101,15 @@ constexpr int OA_KMAX = 64;  // largest cluster resolved by Rayleigh-Ritz
 // Clusters along the column order (eigenvalue estimates arrive in ascending
 // order up to errors far below delta): consecutive |lam_i - lam_{i-1}| <=
 // delta.  Clusters of 2..OA_KMAX members are listed (begin, size, offset of
-// their k x k blocks); cid[i] is the list index of column i's cluster or -1.
-// meta: [0] number of listed clusters, [1] largest cluster size.
-__global__ void oa_cluster_kernel(int64_t n, const double *lam, const double *dl, int *cid, int *cl, int *meta)
+// their k x k blocks); cid[i] is the list index of column i's cluster or -1;
+// larger clusters go to a second list (begin, size) resolved on the host side.
+// meta: [0] listed small clusters, [1] largest cluster size, [2] large clusters.
+__global__ void oa_cluster_kernel(int64_t n, const double *lam, const double *dl, int *cid, int *cl, int *meta,
+                                  int *big)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double delta = dl[0];
-    int ncl = 0, kmax = 1;
+    int ncl = 0, kmax = 1, nbig = 0;
     int64_t off = 0;
     int64_t b0 = 0;
     for (int64_t i = 1; i <= n; ++i) {
@@ -117,12 +124,17 @@ __global__ void oa_cluster_kernel(int64_t n, const double *lam, const double *dl
                 cl[3 * ncl + 2] = (int)off;
                 off += (int64_t)k * k;
                 ++ncl;
+            } else if (k > OA_KMAX) {
+                big[2 * nbig + 0] = (int)b0;
+                big[2 * nbig + 1] = k;
+                ++nbig;
             }
             b0 = i;
         }
     }
     meta[0] = ncl;
     meta[1] = kmax;
+    meta[2] = nbig;
 }
 
 // Rayleigh-Ritz on one cluster per workgroup: N = I + R_CC/2, M = N S_CC N,
@@ -318,6 +330,36 @@ __global__ __launch_bounds__(256) void oa_diagfix_kernel(double *M, int64_t n, c
     }
 }
 
+// N = I + R_CC / 2 for a large cluster (k x k, leading dimension k)
+__global__ void oa_make_n_kernel(int64_t k, const double *Rc, int64_t ldr, double *N)
+{
+    const int64_t total = k * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = idx % k, c = idx / k;
+        N[idx] = ((a == c) ? 1.0 : 0.0) + 0.5 * Rc[a + c * ldr];
+    }
+}
+
+__global__ void oa_copy2d_kernel(int64_t m, int64_t ncol, const double *src, int64_t lds, double *dst, int64_t ldd)
+{
+    const int64_t total = m * ncol;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % m, j = idx / m;
+        dst[i + j * ldd] = src[i + j * lds];
+    }
+}
+
+// M_CC += sign * (I or W): mode 0 adds I, mode 1 adds W - I
+__global__ void oa_add_block_kernel(int64_t k, double *Mc, int64_t ldm, const double *W, int mode)
+{
+    const int64_t total = k * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = idx % k, c = idx / k;
+        const double id = (a == c) ? 1.0 : 0.0;
+        Mc[a + c * ldm] += (mode == 0) ? id : W[idx] - id;
+    }
+}
+
 // E_ij as in RefSyEv from the symmetric parts of S and R (the computed
 // products are symmetric only up to rounding; the asymmetric part divided by
 // a small eigenvalue gap would break the orthogonality E_ij + E_ji = r_ij).
@@ -400,11 +442,24 @@ constexpr int OA_BLOCKS = 1024;
 
 }  // namespace
 
+size_t dsyevd_work_bytes_any_b(int64_t n);
+
 namespace {
+
+// Large clusters (more than OA_KMAX members) are resolved with the FP64
+// two-stage solver on their k x k block; their blocks share one store of
+// OA_BIG_FRAC^2 n^2 doubles (clusters that no longer fit stay unresolved).
+constexpr double OA_BIG_FRAC = 0.75;
+
+int64_t big_capacity(int64_t n) { return n > OA_KMAX ? (int64_t)(OA_BIG_FRAC * (double)n) : 0; }
 
 struct RefWork {
     double *R, *AX, *S, *Xn, *part, *Wg;
-    int *cid, *cl, *meta;
+    int *cid, *cl, *meta, *big;
+    double *bN, *bM, *bW, *bmu;
+    void *bws;
+    size_t bws_bytes;
+    int64_t kcap;
 };
 
 size_t ref_layout(int64_t n, char *base, RefWork *w)
@@ -413,7 +468,7 @@ size_t ref_layout(int64_t n, char *base, RefWork *w)
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char *p = base ? base + off : nullptr;
-        off += evd_align256(bytes);
+        off += evd_align256(bytes > 0 ? bytes : 1);
         return (void *)p;
     };
     RefWork t;
@@ -426,27 +481,112 @@ size_t ref_layout(int64_t n, char *base, RefWork *w)
     t.cid = (int *)take(nn * 4);
     t.cl = (int *)take(nn * 3 * 4);
     t.meta = (int *)take(64);
+    t.big = (int *)take(nn * 2 * 4);
+    t.kcap = big_capacity(n);
+    const size_t kc = (size_t)t.kcap;
+    t.bN = (double *)take(kc * kc * 8);
+    t.bM = (double *)take(kc * kc * 8);
+    t.bW = (double *)take(kc * kc * 8);
+    t.bmu = (double *)take(kc * 8);
+    t.bws_bytes = kc > 0 ? dsyevd_work_bytes_any_b((int64_t)kc) : 0;
+    t.bws = take(t.bws_bytes);
     if (w) *w = t;
     return off;
+}
+
+struct BigC {
+    int64_t b0, k;
+    double *W;
+};
+
+// Rayleigh-Ritz of the large clusters (host loop; reads the cluster list back):
+// N = I + R_CC/2, N S_CC N = V diag(mu) V^T by evd_dsyevd, W = N V; then
+// S' and R' in the rotated basis for those clusters.
+evd_status_t big_clusters_begin(evd_ctx_t ctx, int64_t n, double *S, double *R, double *lam, RefWork &w,
+                                std::vector<BigC> &done)
+{
+    hipStream_t s = ctx->stream;
+    done.clear();
+    if (w.kcap <= 0) return EVD_OK;
+    int hm[4] = {0, 0, 0, 0};
+    EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(hm, w.meta, sizeof(hm), hipMemcpyDeviceToHost, s)));
+    EVD_CHECK(evd_hip(ctx, hipStreamSynchronize(s)));
+    const int nbig = hm[2];
+    if (nbig <= 0) return EVD_OK;
+    std::vector<int> bl(2 * (size_t)nbig);
+    EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(bl.data(), w.big, bl.size() * sizeof(int), hipMemcpyDeviceToHost, s)));
+    EVD_CHECK(evd_hip(ctx, hipStreamSynchronize(s)));
+    const dim3 g(256), t(256);
+    size_t used = 0;
+    const size_t capacity = (size_t)w.kcap * (size_t)w.kcap;
+    const int64_t saved_timing = ctx->timing;
+    for (int q = 0; q < nbig; ++q) {
+        const int64_t b0 = bl[2 * q], k = bl[2 * q + 1];
+        if (k > w.kcap || used + (size_t)(k * k) > capacity) continue;
+        double *Wk = w.bW + used;
+        hipLaunchKernelGGL(oa_make_n_kernel, g, t, 0, s, k, (const double *)(R + b0 + b0 * n), n, w.bN);
+        // T = S_CC N (in the W slot), M = N T
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, k, k, k, 1.0, S + b0 + b0 * n, n, w.bN, k, 0.0, Wk, k, nullptr, 0));
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, k, k, k, 1.0, w.bN, k, Wk, k, 0.0, w.bM, k, nullptr, 0));
+        ctx->timing = 0;
+        const evd_status_t st = evd_dsyevd(ctx, 'V', 'L', k, w.bM, k, w.bmu, w.bws, w.bws_bytes, w.meta + 4);
+        ctx->timing = saved_timing;
+        EVD_CHECK(st);
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, k, k, k, 1.0, w.bN, k, w.bM, k, 0.0, Wk, k, nullptr, 0));
+        hipLaunchKernelGGL(oa_copy2d_kernel, dim3(64), t, 0, s, k, (int64_t)1, (const double *)w.bmu, k, lam + b0, k);
+        done.push_back({b0, k, Wk});
+        used += (size_t)(k * k);
+    }
+    // S' = W^T S W and R' = W^T R W on the resolved clusters' rows and columns
+    for (const BigC &c : done) {
+        for (int which = 0; which < 2; ++which) {
+            double *M = which ? R : S;
+            EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, c.k, c.k, 1.0, M + c.b0 * n, n, c.W, c.k, 0.0, w.Xn, n, nullptr, 0));
+            hipLaunchKernelGGL(oa_copy2d_kernel, g, t, 0, s, n, c.k, (const double *)w.Xn, n, M + c.b0 * n, n);
+            EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, c.k, n, c.k, 1.0, c.W, c.k, M + c.b0, n, 0.0, w.Xn, c.k, nullptr, 0));
+            hipLaunchKernelGGL(oa_copy2d_kernel, g, t, 0, s, c.k, n, (const double *)w.Xn, c.k, M + c.b0, n);
+        }
+        // R'_CC = I - W^T (I - R_CC) W = (W^T R_CC W) + I - W^T W
+        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, c.k, c.k, c.k, -1.0, c.W, c.k, c.W, c.k, 1.0, R + c.b0 + c.b0 * n, n,
+                           nullptr, 0));
+        hipLaunchKernelGGL(oa_add_block_kernel, g, t, 0, s, c.k, R + c.b0 + c.b0 * n, n, (const double *)c.W, 0);
+    }
+    return evd_hip(ctx, hipGetLastError());
+}
+
+// F = W (I + E') - I on the large clusters' rows: E(C, :) <- W E(C, :), E_CC += W - I
+evd_status_t big_clusters_end(evd_ctx_t ctx, int64_t n, double *E, RefWork &w, const std::vector<BigC> &done)
+{
+    hipStream_t s = ctx->stream;
+    const dim3 g(256), t(256);
+    for (const BigC &c : done) {
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, c.k, n, c.k, 1.0, c.W, c.k, E + c.b0, n, 0.0, w.Xn, c.k, nullptr, 0));
+        hipLaunchKernelGGL(oa_copy2d_kernel, g, t, 0, s, c.k, n, (const double *)w.Xn, c.k, E + c.b0, n);
+        hipLaunchKernelGGL(oa_add_block_kernel, g, t, 0, s, c.k, E + c.b0 + c.b0 * n, n, (const double *)c.W, 1);
+    }
+    return evd_hip(ctx, hipGetLastError());
 }
 
 }  // namespace
 
 size_t refine_work_bytes(int64_t n) { return ref_layout(n, nullptr, nullptr); }
 
-// One or more RefSyEv sweeps on X (n x n, ldx), A lower-stored FP64.
-// lam (n) receives the refined eigenvalue estimates.  stats (device, 8
-// doubles): [0] delta, [1] ||S - diag(lam)||_F, [2] ||R||_F, [3] max|lam| of
-// the last sweep, [4] residual ||A X - X lam||_F / (n ||A||_F) of the final X,
-// whose Rayleigh quotients are returned in lam, [5] clusters resolved by
-// Rayleigh-Ritz and [6] the largest cluster size in the last sweep.
-evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
+// One or more RefSyEv sweeps on X (n x n, ldx), A lower-stored FP64, on the
+// context's stream.  lam (n) receives the refined eigenvalue estimates.
+// stats (device, 8 doubles): [0] delta, [1] ||S - diag(lam)||_F, [2] ||R||_F,
+// [3] max|lam| of the last sweep, [4] residual ||A X - X lam||_F / (n ||A||_F)
+// of the final X, whose Rayleigh quotients are returned in lam, [5] clusters
+// resolved by Rayleigh-Ritz and [6] the largest cluster size in the last sweep.
+// Large clusters make the call synchronise with the stream once per sweep.
+evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
                         int sweeps, void *work, double *stats)
 {
+    hipStream_t s = ctx->stream;
     RefWork w;
     ref_layout(n, (char *)work, &w);
     double *R = w.R, *AX = w.AX, *S = w.S, *Xn = w.Xn, *part = w.part;
     const dim3 g(OA_BLOCKS), t(256);
+    std::vector<BigC> big;
     for (int sw = 0; sw < sweeps; ++sw) {
         hipLaunchKernelGGL(oa_eye_kernel, g, t, 0, s, n, R, n);
         EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, n, n, n, -1.0, X, ldx, X, ldx, 1.0, R, n, nullptr, 0));
@@ -455,9 +595,9 @@ evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, 
         hipLaunchKernelGGL(oa_lambda_kernel, dim3(64), t, 0, s, n, (const double *)S, (const double *)R, lam);
         hipLaunchKernelGGL(oa_norms_kernel, g, t, 0, s, n, (const double *)S, (const double *)R, (const double *)lam,
                            part);
-        hipLaunchKernelGGL(oa_delta_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, (const double *)part, stats);
+        hipLaunchKernelGGL(oa_delta_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, n, (const double *)part, stats);
         hipLaunchKernelGGL(oa_cluster_kernel, dim3(1), dim3(64), 0, s, n, (const double *)lam, (const double *)stats,
-                           w.cid, w.cl, w.meta);
+                           w.cid, w.cl, w.meta, w.big);
         // Rayleigh-Ritz on the clusters, then S' = Wbd^T S Wbd, R' = I - Wbd^T (I - R) Wbd
         const unsigned maxcl = (unsigned)(n / 2 < 1024 ? (n / 2 > 0 ? n / 2 : 1) : 1024);
         const dim3 gr((unsigned)evd_ceil_div(n, 256), maxcl < 64 ? maxcl : 64);
@@ -472,6 +612,7 @@ evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, 
         }
         hipLaunchKernelGGL(oa_diagfix_kernel, dim3(maxcl), t, 0, s, R, n, (const int *)w.cl, (const int *)w.meta,
                            (const double *)w.Wg, 0);
+        EVD_CHECK(big_clusters_begin(ctx, n, S, R, lam, w, big));
         // E' in the rotated basis, then F = Wbd (I + E') - I
         double *E = AX;  // A X is no longer needed
         hipLaunchKernelGGL(oa_e_kernel, g, t, 0, s, n, (const double *)S, (const double *)R, (const double *)lam,
@@ -480,6 +621,7 @@ evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, 
                            (const double *)w.Wg, 0);
         hipLaunchKernelGGL(oa_diagfix_kernel, dim3(maxcl), t, 0, s, E, n, (const int *)w.cl, (const int *)w.meta,
                            (const double *)w.Wg, 1);
+        EVD_CHECK(big_clusters_end(ctx, n, E, w, big));
         hipLaunchKernelGGL(oa_meta_stats_kernel, dim3(1), dim3(64), 0, s, (const int *)w.meta, stats);
         hipLaunchKernelGGL(oa_copy_kernel, g, t, 0, s, n, (const double *)X, ldx, Xn, n);
         EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, X, ldx, E, n, 1.0, Xn, n, nullptr, 0));
@@ -492,5 +634,5 @@ evd_status_t refine_run(hipStream_t s, int64_t n, const double *A, int64_t lda, 
     hipLaunchKernelGGL(oa_resid_kernel, g, t, 0, s, n, (const double *)AX, (const double *)X, (const double *)lam, A,
                        lda, part);
     hipLaunchKernelGGL(oa_resid_final_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, n, (const double *)part, stats + 4);
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_hip(ctx, hipGetLastError());
 }

@@ -4,9 +4,13 @@
 //   1. panel QR  P_k = (I - Y T Y^T) R  (cooperative kernel below);
 //   2. W = Y T;  X = A_2 W (symmetric A_2 read from its lower triangle);
 //      M = W^T X;  Z = X - 1/2 Y M                          (Eq. 1, first line)
-//   3. A_2 <- A_2 - Y Z^T - Z Y^T as ONE rank-2b product [Y Z][Z Y]^T on the
-//      lower triangle                                        (Eq. 1, second line)
-// The updated trailing matrix is the next panel's input (Section 2.1.1).
+//   3. A_2 <- A_2 - Y Z^T - Z Y^T                             (Eq. 1, second line)
+// With double blocking (Section 4.1) the update of step 3 is deferred over an
+// outer block of q panels: the accumulators hold [Y_0 Z_0 Y_1 Z_1 ...] and
+// [Z_0 Y_0 Z_1 Y_1 ...], so any prefix of them is a consistent rank-2jb
+// update; each panel's columns are brought up to date just before its QR,
+// A_2 W is corrected for the deferred part, and one rank-2qb product on the
+// lower triangle per outer block updates the trailing matrix.
 //
 // Panel QR: the m x b panel is split into row chunks, one workgroup per chunk
 // holding its rows in LDS for the whole factorization.  Column j needs one
@@ -59,7 +63,7 @@ __global__ void extract_diag_blocks_kernel(int64_t n, int64_t b, int64_t tail0, 
 
 template <int B, typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, T *P, int64_t lda,
-                                                                 T *YZY, int64_t ldy, T *part,
+                                                                 T *Y1, T *Y2, int64_t ldy, T *part,
                                                                  T *Sg, T *taus, T *Tout,
                                                                  T *AB, int64_t ldab, int64_t j0, int *flags,
                                                                  int epoch0)
@@ -192,15 +196,16 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
         __syncthreads();
     }
 
-    // ---- write back: explicit Y into the panel of A and into [Y | Z | Y]
+    // ---- write back: explicit Y into the panel of A and into the two
+    // accumulator slots of the outer block
     for (int e = tid; e < rows * B; e += PANEL_THREADS) {
         const int i = e % rows, q = e / rows;
         const int64_t gi = r0 + i;
         T y = 0.0;
         if (q < nr) y = (gi > q) ? Ps[q * ldp + i] : (gi == q ? 1.0 : 0.0);
         P[gi + (int64_t)q * lda] = y;
-        YZY[gi + (int64_t)q * ldy] = y;
-        YZY[gi + (int64_t)(2 * B + q) * ldy] = y;
+        Y1[gi + (int64_t)q * ldy] = y;
+        Y2[gi + (int64_t)q * ldy] = y;
     }
     if (g != 0) return;
     // R (upper trapezoid of the first nr rows) -> band storage
@@ -230,7 +235,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
 }
 
 template <int B, typename T>
-evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *YZY, int64_t ldy, T *part,
+evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
                           T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
 {
     int maxg = PANEL_MAX_WGS;
@@ -245,42 +250,49 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *YZY, i
     if (lds < (size_t)B * B * sizeof(T)) lds = (size_t)B * B * sizeof(T);
     if (lds > 150 * 1024) return EVD_ERR_INVALID_ARG;
     int chunk_i = (int)chunk;
-    void *args[] = {&m, &chunk_i, &P, (void *)&lda, &YZY, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
+    void *args[] = {&m, &chunk_i, &P, (void *)&lda, &Y1, &Y2, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
                     (void *)&ldab, (void *)&j0, &bar, &epoch0};
     hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3(G), dim3(PANEL_THREADS), args,
                                               (unsigned)lds, ctx->stream);
-    return e == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_hip(ctx, e);
 }
 
 template <typename T>
-evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, T *P, int64_t lda, T *YZY, int64_t ldy, T *part,
+evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
                             T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
 {
     switch (b) {
-    case 1: return launch_panel<1, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 2: return launch_panel<2, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 4: return launch_panel<4, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 8: return launch_panel<8, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 16: return launch_panel<16, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 32: return launch_panel<32, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 64: return launch_panel<64, T>(ctx, m, P, lda, YZY, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 1: return launch_panel<1, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 2: return launch_panel<2, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 4: return launch_panel<4, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 8: return launch_panel<8, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 16: return launch_panel<16, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 32: return launch_panel<32, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 64: return launch_panel<64, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
     default: return EVD_ERR_INVALID_ARG;
     }
 }
 
 template <typename T>
 struct SbrWork {
-    T *YZY;   // n x 3b
-    T *X;     // unused (Z is formed in place)
+    T *YZ;    // [Y_0 Z_0 Y_1 Z_1 ...] of the outer block, n x 2nb
+    T *ZY;    // [Z_0 Y_0 Z_1 Y_1 ...], n x 2nb
     T *W;     // n x b
     T *M;     // b x b
+    T *U;     // 2nb x b
     T *part;  // reduction scratch of the panel kernel
     T *Sg;    // b x b
     T *taus;  // b
     T *gemm_ws;
     size_t gemm_ws_elems;
-    int *bar;  // grid barrier state of the panel kernel
+    int *bar;  // flags of the panel kernel
+    int64_t q;  // panels per outer block
 };
+
+// Outer block of SBR: SBR_NB columns (at least one panel).
+constexpr int64_t SBR_NB = 256;
+
+inline int64_t sbr_panels_per_block(int64_t b) { return (SBR_NB / b) > 0 ? SBR_NB / b : 1; }
 
 template <typename T>
 size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
@@ -288,21 +300,26 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     size_t off = 0;
     auto take = [&](size_t elems) {
         char *p = base ? base + off : nullptr;
-        off += evd_align256(elems * sizeof(T));
+        off += evd_align256((elems > 0 ? elems : 1) * sizeof(T));
         return (T *)p;
     };
     SbrWork<T> t;
-    t.YZY = take((size_t)n * 3 * b);
+    t.q = sbr_panels_per_block(b);
+    const int64_t nb = t.q * b;
+    t.YZ = take((size_t)n * 2 * nb);
+    t.ZY = take((size_t)n * 2 * nb);
     t.W = take((size_t)n * b);
     t.M = take((size_t)b * b);
+    t.U = take((size_t)2 * nb * b);
     t.part = take((size_t)PANEL_MAX_WGS * b + 2 * b + 64);
     t.Sg = take((size_t)b * b);
     t.taus = take((size_t)b);
-    t.X = nullptr;
-    // split-K workspace for the b x b product W^T Z (K up to n)
+    // split-K workspace for the b x b product W^T X and the 2nb x b product
     size_t ws = gemm_ws_elems_t<T>(b, b, n);
-    size_t ws2 = gemm_ws_elems_t<T>(n, b, n);
+    const size_t ws2 = gemm_ws_elems_t<T>(n, b, n);
+    const size_t ws3 = gemm_ws_elems_t<T>(2 * nb, b, n);
     if (ws2 > ws) ws = ws2;
+    if (ws3 > ws) ws = ws3;
     t.gemm_ws = take(ws);
     t.gemm_ws_elems = ws;
     t.bar = (int *)take((PANEL_MAX_WGS + 64) * sizeof(int) / sizeof(T));
@@ -310,6 +327,35 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     return off;
 }
 
+template <typename T>
+__global__ void fill2d_kernel(int64_t m, int64_t ncol, T *p, int64_t ld)
+{
+    const int64_t total = m * ncol;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        p[(i % m) + (i / m) * ld] = (T)0;
+}
+
+template <typename T>
+__global__ void copy2d_kernel(int64_t m, int64_t ncol, const T *src, int64_t lds, T *dst, int64_t ldd)
+{
+    const int64_t total = m * ncol;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        dst[(i % m) + (i / m) * ldd] = src[(i % m) + (i / m) * lds];
+}
+
+inline dim3 grid_for(int64_t count)
+{
+    const int64_t g = evd_ceil_div(count, 256);
+    return dim3((unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096));
+}
+
+// Double-blocked SBR (the paper's two-level blocking): inside an outer block
+// of q panels the trailing matrix is not updated; each panel's columns are
+// brought up to date just before its QR, its product A_2 W uses the stale
+// trailing matrix corrected by the block's accumulated reflectors,
+//   A_2 W = A_stale W - Y_J (Z_J^T W) - Z_J (Y_J^T W),
+// and one rank-2nb SYR2K per outer block updates the trailing matrix.  With
+// q = 1 this is the single-blocked scheme of Eq. 1.
 template <typename T>
 evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int64_t lda, T *AB, int64_t ldab,
                        T *Tf, void *work)
@@ -328,34 +374,64 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
     }
     hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(256), 0, s, w.bar, (int64_t)(PANEL_MAX_WGS + 1), 0);
     const int64_t p = evd_sbr_num_panels(n, b);
-    for (int64_t k = 0; k < p; ++k) {
-        const int64_t j0 = k * b, i0 = j0 + b, m = n - i0;
-        T *P = A + i0 + j0 * lda;
-        T *A2 = A + i0 + i0 * lda;
-        T *Tk = Tf + k * b * b;
-        const int64_t ldy = m;
-        EVD_CHECK(panel_dispatch<T>(ctx, b, m, P, lda, w.YZY, ldy, w.part, w.Sg, w.taus, Tk, AB, ldab, j0, w.bar,
-                                    (int)(k * (b + 1))));
-        T *Y = w.YZY, *Zs = w.YZY + b * ldy;
-        // W = Y T
-        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)1, Y, ldy, Tk, b, (T)0, w.W, m, (T *)nullptr, 0));
-        // X = A_2 W  (into the Z slot)
-        EVD_CHECK(gemm_t(s, OP_S, OP_N, 0, m, b, m, (T)1, A2, lda, w.W, m, (T)0, Zs, ldy, w.gemm_ws,
-                           w.gemm_ws_elems));
-        // M = W^T X
-        EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, b, b, m, (T)1, w.W, m, Zs, ldy, (T)0, w.M, b, w.gemm_ws,
-                           w.gemm_ws_elems));
-        // Z = X - 1/2 Y M
-        EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)-0.5, Y, ldy, w.M, b, (T)1, Zs, ldy, (T *)nullptr, 0));
-        // A_2 <- A_2 - [Y Z] [Z Y]^T   (lower triangle)
-        EVD_CHECK(gemm_t(s, OP_N, OP_T, 1, m, m, 2 * b, (T)-1, w.YZY, ldy, Zs, ldy, (T)1, A2, lda, (T *)nullptr, 0));
+    const int64_t q = (ctx->sbr_nb > 0) ? ((ctx->sbr_nb / b) > 0 ? ctx->sbr_nb / b : 1) : w.q;
+    const int64_t qmax = w.q < q ? w.q : q;  // the accumulators hold w.q panels
+    for (int64_t K0 = 0; K0 < p; K0 += qmax) {
+        const int64_t qe = (K0 + qmax <= p) ? qmax : p - K0;
+        const int64_t base = K0 * b + b;        // first row held by the accumulators
+        const int64_t ldc = n - base;           // their leading dimension
+        for (int64_t t = 0; t < qe; ++t) {
+            const int64_t k = K0 + t, j0 = k * b, i0 = j0 + b, m = n - i0;
+            const int64_t ro = i0 - base, jb = t * b;
+            T *Tk = Tf + k * b * b;
+            if (t > 0) {
+                // bring the panel's columns (rows j0..n-1) up to date with the block so far
+                const int64_t rj = j0 - base;
+                EVD_CHECK(gemm_t(s, OP_N, OP_T, 0, n - j0, b, 2 * jb, (T)-1, w.YZ + rj, ldc, w.ZY + rj, ldc, (T)1,
+                                 A + j0 + j0 * lda, lda, (T *)nullptr, 0));
+                // rows of the block above this panel are zero in its Y and Z columns
+                hipLaunchKernelGGL(fill2d_kernel<T>, grid_for(ro * 2 * b), dim3(256), 0, s, ro, 2 * b,
+                                   w.YZ + 2 * t * b * ldc, ldc);
+                hipLaunchKernelGGL(fill2d_kernel<T>, grid_for(ro * 2 * b), dim3(256), 0, s, ro, 2 * b,
+                                   w.ZY + 2 * t * b * ldc, ldc);
+            }
+            T *Y = w.YZ + ro + 2 * t * b * ldc;
+            T *Zs = w.YZ + ro + (2 * t + 1) * b * ldc;
+            T *P = A + i0 + j0 * lda;
+            T *A2 = A + i0 + i0 * lda;
+            EVD_CHECK(panel_dispatch<T>(ctx, b, m, P, lda, Y, w.ZY + ro + (2 * t + 1) * b * ldc, ldc, w.part, w.Sg,
+                                        w.taus, Tk, AB, ldab, j0, w.bar, (int)(k * (b + 1))));
+            // W = Y T
+            EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)1, Y, ldc, Tk, b, (T)0, w.W, m, (T *)nullptr, 0));
+            // X = A_2 W (stale A_2 inside the block) into the Z slot
+            EVD_CHECK(gemm_t(s, OP_S, OP_N, 0, m, b, m, (T)1, A2, lda, w.W, m, (T)0, Zs, ldc, w.gemm_ws,
+                             w.gemm_ws_elems));
+            if (t > 0) {
+                // X -= [Y_J Z_J] ([Z_J Y_J]^T W)
+                EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, 2 * jb, b, m, (T)1, w.ZY + ro, ldc, w.W, m, (T)0, w.U, 2 * jb,
+                                 w.gemm_ws, w.gemm_ws_elems));
+                EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, 2 * jb, (T)-1, w.YZ + ro, ldc, w.U, 2 * jb, (T)1, Zs, ldc,
+                                 (T *)nullptr, 0));
+            }
+            // M = W^T X;  Z = X - 1/2 Y M
+            EVD_CHECK(gemm_t(s, OP_T, OP_N, 0, b, b, m, (T)1, w.W, m, Zs, ldc, (T)0, w.M, b, w.gemm_ws,
+                             w.gemm_ws_elems));
+            EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)-0.5, Y, ldc, w.M, b, (T)1, Zs, ldc, (T *)nullptr, 0));
+            hipLaunchKernelGGL(copy2d_kernel<T>, grid_for(m * b), dim3(256), 0, s, m, b, (const T *)Zs, ldc,
+                               w.ZY + ro + 2 * t * b * ldc, ldc);
+        }
+        // A_2 <- A_2 - [Y Z ...] [Z Y ...]^T on the lower triangle, rank 2 qe b
+        const int64_t iK = (K0 + qe - 1) * b + b, rK = iK - base, mK = n - iK;
+        if (mK > 0)
+            EVD_CHECK(gemm_t(s, OP_N, OP_T, 1, mK, mK, 2 * qe * b, (T)-1, w.YZ + rK, ldc, w.ZY + rK, ldc, (T)1,
+                             A + iK + iK * lda, lda, (T *)nullptr, 0));
     }
     {
         dim3 blk(64, 4);
         hipLaunchKernelGGL(extract_diag_blocks_kernel<T>, dim3((unsigned)evd_ceil_div(n, 4)), blk, 0, s, n, b, p * b,
                            (const T *)A, lda, AB, ldab);
     }
-    return hipGetLastError() == hipSuccess ? EVD_OK : EVD_ERR_HIP;
+    return evd_check_last();
 }
 
 }  // namespace
@@ -411,7 +487,7 @@ evd_status_t evd_dsy2sb(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *
     if (bad) return bad == 11 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
-    if (hipSetDevice(ctx->device) != hipSuccess) return EVD_ERR_HIP;
+    EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
     return sbr_run(ctx, uplo, n, b, A, lda, AB, ldab, T, work);
 }
 

@@ -309,8 +309,7 @@ def eigh_mixed(A, sweeps: int = 2, uplo: str = "L", b: int = 0, ctx: Context | N
 
     n = A.shape[0]
     ctx = ctx or context(A.device.index or 0)
-    if b:
-        ctx.set_param("b", b)
+    ctx.set_param("b", b)  # 0 = automatic
     Acm = A.t().contiguous().t()
     Acm = Acm.clone() if Acm.data_ptr() == A.data_ptr() else Acm
     W = torch.empty(max(n, 1), dtype=torch.float64, device=A.device)
@@ -337,8 +336,7 @@ def eigh(A, jobz: str = "V", uplo: str = "L", b: int = 0, ctx: Context | None = 
     if A.shape[1] != n:
         raise ValueError("A must be square")
     ctx = ctx or context(A.device.index or 0)
-    if b:
-        ctx.set_param("b", b)
+    ctx.set_param("b", b)  # 0 = automatic
     # column-major copy: the transpose of a contiguous row-major tensor
     Acm = A.t().contiguous().t() if n > 0 else A.clone()
     Acm = Acm.clone() if Acm.data_ptr() == A.data_ptr() else Acm

@@ -33,13 +33,31 @@ def run_batched(ctx, mats, graph=1, streams=4, reps=1):
         for a, p in zip(As, pristine):
             a.copy_(p)                      # eager work between replays
         torch.cuda.synchronize()
-        ctx.evd_dsyevd_batched("V", "L", ns, As, ns, Ws, work, wb, info, stamps)
+        ctx.set_param("last_hip_error", 0)
+        try:
+            ctx.evd_dsyevd_batched("V", "L", ns, As, ns, Ws, work, wb, info, stamps)
+        finally:
+            print("hip error:", ctx.get_param("last_hip_error"), "capture error:", ctx.get_param("capture_error"),
+                  "graph used:", ctx.get_param("last_graph_used"))
         torch.cuda.synchronize()
         outs.append(([w[:n].cpu().numpy() for w, n in zip(Ws, ns)],
                      [a.cpu().numpy().T.copy() for a in As], info.cpu().numpy().copy(),
                      stamps.cpu().numpy().copy(), ctx.get_param("last_graph_used")))
     ctx.set_param("batch_graph", 1)
     return outs
+
+
+def test_batched_direct_single_stream():
+    """One internal stream, no graph: the plainest form of the batched call."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    Ls, mats = make_batch(5, seed=3, lmin=3, lmax=8)
+    ws, Qs, info, stamps, used = run_batched(ctx, mats, graph=0, streams=1, reps=1)[0]
+    ctx.set_param("batch_streams", 0)
+    assert used == 0 and np.all(info == 0)
+    for A, w, Q in zip(mats, ws, Qs):
+        assert M.eig_error(w, oracle.syev(A, jobz="N")) <= 1e-12
+        assert M.residual(A, w, Q) <= 10 and M.orthogonality(Q) <= 10
 
 
 def test_batched_tight_binding_vs_oracle():

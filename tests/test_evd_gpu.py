@@ -109,3 +109,42 @@ def test_trace_frobenius_invariants():
     w, _ = gpu_eigh(A, jobz="N")
     assert abs(w.sum() - np.trace(A)) <= 1e-12 * 800
     assert abs((w ** 2).sum() - (A ** 2).sum()) <= 1e-12 * (A ** 2).sum()
+
+
+@pytest.mark.parametrize("n,b", [(5, 4), (130, 8), (300, 32), (700, 64), (1000, 32)])
+def test_conventional_stage_order(n, b):
+    """order = 1: Q = Q_s (H_1 ... H_m Q_d) with the reverse-order BC-back and
+    SBR-back applied from the left; same gates as the reordered stages."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    A = W.gaussian_sym(n, seed=n + 3 * b)
+    try:
+        ctx.set_param("order", 1)
+        w, Q = gpu_eigh(A, b=b)
+    finally:
+        ctx.set_param("order", 0)
+    check(A, w, Q, oracle.syev(A, jobz="N"))
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("n,b", [(300, 16), (515, 32), (700, 64), (1100, 64)])
+def test_blocked_bcback_matches_reflector_by_reflector(n, b, order):
+    """The blocked BC-back on the matrix cores (groups of 32 sweeps, compact
+    WY) and the reflector-by-reflector kernel give the same eigenvectors up to
+    rounding, in both stage orders."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    A = W.gaussian_sym(n, seed=n + b + order)
+    out = []
+    try:
+        ctx.set_param("order", order)
+        for valu in (0, 1):
+            ctx.set_param("bcback_valu", valu)
+            out.append(gpu_eigh(A, b=b))
+    finally:
+        ctx.set_param("order", 0)
+        ctx.set_param("bcback_valu", 0)
+    (w0, Q0), (w1, Q1) = out
+    assert np.array_equal(w0, w1)
+    assert np.abs(Q0 - Q1).max() <= 1e-12
+    check(A, w0, Q0, oracle.syev(A, jobz="N"))

@@ -58,7 +58,7 @@ def test_mixed_refined_gaussian(n, seed):
 def test_mixed_known_spectrum_well_separated():
     n = 600
     A, lam = W.known_spectrum(n, seed=5, spectrum="uniform", reflectors=16)
-    w, Q, st = run_mixed(A, sweeps=2, b=32)
+    w, Q, st = run_mixed(A, sweeps=3, b=32)
     assert M.eig_error(w, lam) <= 1e-12
     assert scaled_res(A, w, Q) <= 1e-13 and scaled_orth(Q) <= 1e-13
 
