@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--jobz", default="V")
     ap.add_argument("--order", type=int, default=1,
                     help="0 = reordered stages (Q_s H.. then Q_sb Q_d), 1 = conventional (Q_s (H.. Q_d))")
+    ap.add_argument("--bcback-valu", type=int, default=0,
+                    help="1 = reflector-by-reflector BC-back on the vector ALUs instead of the blocked MFMA kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     args = ap.parse_args()
@@ -82,6 +84,7 @@ def main():
     ctx.set_param("b", b)
     ctx.set_param("timing", 1)
     ctx.set_param("order", args.order)
+    ctx.set_param("bcback_valu", args.bcback_valu)
 
     log(f"[bench] generating n={n} on the GPU")
     g = torch.Generator(device=dev)

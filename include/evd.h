@@ -70,6 +70,8 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "bcback_valu"  1 = apply the bulge-chasing reflectors one by one on the
  *                  vector ALUs; 0 (default) = in blocks of 32 sweeps on the
  *                  matrix cores (b = 16, 32, 64)
+ *   "orgsb_nb"     panels of b columns aggregated into one block reflector in
+ *                  SBR-back, in columns (0 = 512)
  *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 256;
  *                  a value <= b gives single blocking (one update per panel)
  *   "last_hip_error" first HIP error code a call met (read; set 0 to clear)
@@ -197,7 +199,11 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
  *   AB (ldab >= 2b+1, n columns): B in lower band storage, AB[d + j*ldab] =
  *      B(j+d, j) for 0 <= d <= b; rows b+1..2b are zeroed (room for bulges).
  *   A: columns kb..kb+b-1, rows (k+1)b..n-1 hold the explicit Y_k
- *      (unit lower trapezoidal: ones on its diagonal, zeros above).
+ *      (unit lower trapezoidal: ones on its diagonal, zeros above); the rest
+ *      of A (both triangles) is used as scratch.
+ * The trailing updates are double-blocked (Section 4.1): deferred over outer
+ * blocks of "sbr_nb" columns, with the trailing matrix mirrored into full
+ * storage at the start of each block so that A_2 W is a plain product.
  *   T: the b x b upper triangular T_k of panel k at T + k*b*b (column-major,
  *      leading dimension b); evd_sbr_num_panels(n, b) panels.
  * Requires 1 <= b <= 64, b | 64 (b in {1,2,4,8,16,32,64}). */

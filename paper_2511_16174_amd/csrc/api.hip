@@ -86,6 +86,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "panel_wgs")) return &ctx->panel_wgs;
     if (!strcmp(key, "sbr_nb")) return &ctx->sbr_nb;
     if (!strcmp(key, "bcback_valu")) return &ctx->bcback_valu;
+    if (!strcmp(key, "orgsb_nb")) return &ctx->orgsb_nb;
     if (!strcmp(key, "batch_streams")) return &ctx->batch_streams;
     if (!strcmp(key, "batch_graph")) return &ctx->batch_graph;
     if (!strcmp(key, "last_graph_used")) return &ctx->last_graph_used;

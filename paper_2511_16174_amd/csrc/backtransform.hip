@@ -69,16 +69,27 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
     for (int e = tid; e < 2 * G * LDV; e += BCB_THREADS) (&vs[0][0][0])[e] = 0.0;
     __syncthreads();
 
-    auto load_group = [&](int buf, int64_t c0, int64_t s) {
-        for (int e = tid; e < G * B; e += BCB_THREADS) {
-            const int jj = e / B, i = e % B;
+    // the next group is fetched into registers before the current one is
+    // applied and written to LDS after it (the fetch latency overlaps the work)
+    constexpr int NV = (G * B + BCB_THREADS - 1) / BCB_THREADS;
+    T gv[NV], gt = 0.0;
+    auto fetch_group = [&](int64_t c0, int64_t s) {
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+            const int e = tid + r * BCB_THREADS, jj = e / B, i = e % B;
             const int64_t c = c0 + jj;
-            vs[buf][jj][VPAD + i] = (c < nsweeps && s < nsteps) ? V[((s * n) + c) * B + i] : 0.0;
+            gv[r] = (e < G * B && c < nsweeps && s < nsteps) ? V[((s * n) + c) * B + i] : (T)0;
         }
-        for (int jj = tid; jj < G; jj += BCB_THREADS) {
-            const int64_t c = c0 + jj;
-            ts[buf][jj] = (c < nsweeps && s < nsteps) ? TAU[s * n + c] : 0.0;
+        const int64_t c = c0 + tid;
+        gt = (tid < G && c < nsweeps && s < nsteps) ? TAU[s * n + c] : (T)0;
+    };
+    auto store_group = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+            const int e = tid + r * BCB_THREADS, jj = e / B, i = e % B;
+            if (e < G * B) vs[buf][jj][VPAD + i] = gv[r];
         }
+        if (tid < G) ts[buf][tid] = gt;
     };
     // one reflector of the current group applied to the lane's window slots
     auto apply = [&](int buf, T(&x)[NW], auto jjc) {
@@ -118,7 +129,8 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
             x[k] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
         }
         __syncthreads();
-        load_group(0, c0, REV ? 0 : S - 1);
+        fetch_group(c0, REV ? 0 : S - 1);
+        store_group(0);
         __syncthreads();
         int buf = 0;
         for (int64_t it = 0; it < S; ++it) {
@@ -132,12 +144,13 @@ __global__ __launch_bounds__(ROWS * 4) void bcback_kernel(int64_t mrows, int64_t
                     const int64_t col = REV ? base + B + 4 * (NW - SH + k) + rho : base - B + 4 * k + rho;
                     pre[k] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
                 }
-                load_group(buf ^ 1, c0, REV ? s + 1 : s - 1);
+                fetch_group(c0, REV ? s + 1 : s - 1);
             }
             // the G reflectors of step s: sweeps ascending (descending for REV)
             for_each_reflector<G, REV>([&](auto jjc) { apply(buf, x, jjc); }, std::make_integer_sequence<int, G>{});
             // slide: columns leaving the window go back to memory
             if (more) {
+                store_group(buf ^ 1);
                 if (REV) {
 #pragma unroll
                     for (int k = 0; k < SH; ++k) {
@@ -275,7 +288,7 @@ evd_status_t bcback_run_f32(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, 
 // I - Y_g T_g Y_g^T (T_g from the recurrence T = [[T1, -T1 Y1^T Y2 T2], [0, T2]]),
 // so the two large products of each group have inner dimension ORGSB_NB
 // rather than b.
-constexpr int64_t ORGSB_NB = 256;
+constexpr int64_t ORGSB_NB = 512;  // largest group (columns); "orgsb_nb" may pick a smaller one
 
 namespace {
 
@@ -352,8 +365,11 @@ evd_status_t orgsb_run_t(evd_ctx_t ctx, int64_t n, int64_t b, const T *A, int64_
     OrgsbWork<T> w;
     orgsb_layout<T>(n, b, (char *)work, &w);
     const int64_t p = evd_sbr_num_panels(n, b);
-    const int64_t gp = orgsb_group_panels(b);
-    const int64_t nb = gp * b;
+    const int64_t gpmax = orgsb_group_panels(b);
+    const int64_t nb = gpmax * b;  // leading dimension of the group buffers
+    int64_t gp = (ctx->orgsb_nb > 0) ? ctx->orgsb_nb / b : gpmax;
+    if (gp < 1) gp = 1;
+    if (gp > gpmax) gp = gpmax;
     const int64_t ngroups = evd_ceil_div(p, gp);
     for (int64_t g = ngroups - 1; g >= 0; --g) {
         const int64_t k0 = g * gp;

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
     constexpr int LDY = G + 1;
     constexpr int LDT = G + 1;
     static_assert(W % 16 == 0, "window must be a whole number of 16-column tiles");
+    static_assert((G * B) % 256 == 0 && (G * G) % 256 == 0, "group operands must split evenly over the threads");
     __shared__ double Ys[2][W][LDY];
     __shared__ double Ts[2][G][LDT];
 
@@ -106,15 +107,34 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
     for (int e = tid; e < 2 * W * LDY; e += 256) (&Ys[0][0][0])[e] = 0.0;
     __syncthreads();
 
-    auto load_group = [&](int buf, int64_t blk, int64_t s) {
+    // a group's operands are fetched into registers before the current group
+    // is applied and written to LDS after it, so the fetch latency overlaps
+    // the matrix-core work
+    constexpr int NV = G * B / 256, NT = G * G / 256;
+    double gv[NV], gt[NT];
+    auto fetch_group = [&](int64_t blk, int64_t s) {
         const int64_t c0 = blk * G;
-        for (int e = tid; e < G * B; e += 256) {
-            const int j = e / B, i = e % B;
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+            const int e = tid + r * 256, j = e / B, i = e % B;
             const int64_t c = c0 + j;
-            Ys[buf][j + i][j] = (c < nsweeps && s < nsteps) ? V[((s * n) + c) * B + i] : 0.0;
+            gv[r] = (c < nsweeps && s < nsteps) ? V[((s * n) + c) * B + i] : 0.0;
         }
         const double *T = Tg + (s * nblk + blk) * (int64_t)(G * G);
-        for (int e = tid; e < G * G; e += 256) Ts[buf][e / G][e % G] = T[e];
+#pragma unroll
+        for (int r = 0; r < NT; ++r) gt[r] = T[tid + r * 256];
+    };
+    auto store_group = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+            const int e = tid + r * 256, j = e / B, i = e % B;
+            Ys[buf][j + i][j] = gv[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NT; ++r) {
+            const int e = tid + r * 256;
+            Ts[buf][e / G][e % G] = gt[r];
+        }
     };
 
     double x[KW];
@@ -132,7 +152,8 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
             x[kk] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
         }
         __syncthreads();
-        load_group(0, blk, REV ? 0 : S - 1);
+        fetch_group(blk, REV ? 0 : S - 1);
+        store_group(0);
         __syncthreads();
         int buf = 0;
         for (int64_t it = 0; it < S; ++it) {
@@ -144,7 +165,7 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
                     const int64_t col = REV ? base + B + 4 * (KW - SHK + k) + lk : base - B + 4 * k + lk;
                     pre[k] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
                 }
-                load_group(buf ^ 1, blk, REV ? s + 1 : s - 1);
+                fetch_group(blk, REV ? s + 1 : s - 1);
             }
             // P = Q_w Y: reflector tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3
             double4_t P[2];
@@ -188,6 +209,7 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
                 x[4 * t + 3] = acc[3];
             }
             if (more) {
+                store_group(buf ^ 1);
                 if (REV) {
 #pragma unroll
                     for (int kk = 0; kk < SHK; ++kk) {

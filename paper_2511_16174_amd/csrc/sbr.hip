@@ -2,7 +2,7 @@
 //
 // For panel k (columns j0 = k b .. j0+b-1, rows i0 = j0+b .. n-1, m = n-i0):
 //   1. panel QR  P_k = (I - Y T Y^T) R  (cooperative kernel below);
-//   2. W = Y T;  X = A_2 W (symmetric A_2 read from its lower triangle);
+//   2. W = Y T;  X = A_2 W (A_2 kept in full storage, see below);
 //      M = W^T X;  Z = X - 1/2 Y M                          (Eq. 1, first line)
 //   3. A_2 <- A_2 - Y Z^T - Z Y^T                             (Eq. 1, second line)
 // With double blocking (Section 4.1) the update of step 3 is deferred over an
@@ -10,26 +10,33 @@
 // [Z_0 Y_0 Z_1 Y_1 ...], so any prefix of them is a consistent rank-2jb
 // update; each panel's columns are brought up to date just before its QR,
 // A_2 W is corrected for the deferred part, and one rank-2qb product on the
-// lower triangle per outer block updates the trailing matrix.
+// lower triangle per outer block updates the trailing matrix, which is then
+// mirrored into the upper triangle: inside the next block every A_2 W reads
+// the same stale full matrix with a plain (non-symmetric) product.
 //
 // Panel QR: the m x b panel is split into row chunks, one workgroup per chunk
 // holding its rows in LDS for the whole factorization.  Column j needs one
 // chip-wide reduction: every workgroup publishes the partial sums
 // h_q = sum_{i > j} P(i, j) P(i, q) for all q (its squared norm for q = j,
 // the dot products with the remaining columns for q > j and with the finished
-// reflectors for q < j), workgroup 0 waits for all of them, reduces them and
-// publishes the sums together with row j; from these every workgroup forms
-// the Householder vector and applies it to its rows.  Flags and data crossing
-// workgroups use device-coherent accesses; flags carry an epoch that grows
-// across columns and panels, so nothing is reset between columns.  The T
-// factor (forward, column-wise: T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T
-// v_j)) is formed at the end by workgroup 0 from the reduced Y^T v products.
+// reflectors for q < j), workgroup 0 adds row j; every workgroup waits for all
+// records, sums them in the same fixed order (so all hold bitwise identical
+// sums: one flag round trip per column), forms the Householder vector and
+// applies it to its rows.  Flags and data crossing workgroups use
+// device-coherent accesses; flags carry an epoch that grows across columns
+// and panels (nothing is reset between columns), and the records are double
+// buffered by column parity: a workgroup can only start writing column j+2
+// after every workgroup has published column j+1, i.e. has finished reading
+// column j.  The T factor (forward, column-wise: T[0:j, j] = -tau_j T[0:j, 0:j]
+// (Y[:, 0:j]^T v_j)) is formed at the end by workgroup 0 from the reduced
+// Y^T v products.
 #include "common.h"
 
 namespace {
 
 constexpr int PANEL_THREADS = 256;
 constexpr int PANEL_MAX_WGS = 256;  // workgroups of one panel launch (at most)
+constexpr int PANEL_WGS = 128;      // workgroups of one panel launch (target)
 
 template <typename T>
 __global__ void fill_kernel(T *p, int64_t count, T v)
@@ -39,6 +46,26 @@ __global__ void fill_kernel(T *p, int64_t count, T v)
 }
 
 // A(i, j) <- A(j, i) for i > j  (mirror the stored upper triangle into the lower)
+// A(j, i) <- A(i, j) for i > j on an m x m block (lower triangle -> upper),
+// 32 x 32 tiles through LDS; tiles strictly above the diagonal exit.
+template <typename T>
+__global__ __launch_bounds__(256) void mirror_lower_kernel(int64_t m, T *A, int64_t lda)
+{
+    __shared__ T tile[32][33];
+    const int64_t bi = (int64_t)blockIdx.x * 32, bj = (int64_t)blockIdx.y * 32;  // tile rows bi.., cols bj..
+    if (bi < bj) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bi + tx, j = bj + r;
+        if (i < m && j < m && i > j) tile[r][tx] = A[i + j * lda];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bj + tx, j = bi + r;  // destination (i, j) = source (j, i)
+        if (i < m && j < m && j > i) A[i + j * lda] = tile[tx][r];
+    }
+}
+
 template <typename T>
 __global__ void mirror_upper_kernel(int64_t n, T *A, int64_t lda)
 {
@@ -68,10 +95,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
                                                                  T *AB, int64_t ldab, int64_t j0, int *flags,
                                                                  int epoch0)
 {
-    // part[h*B + q]: partial sums of workgroup h; res = part + PANEL_MAX_WGS*B
-    // holds the reduced sums [0, B) and row j of the panel [B, 2B).
-    // flags[h]: epoch of the last column workgroup h has published partials
-    // for; flags[PANEL_MAX_WGS]: epoch of the last reduction of workgroup 0.
+    // part[(j & 1) * PANEL_MAX_WGS * 2B + h * 2B + q]: record of workgroup h for
+    // column j (double-buffered by column parity): [0, B) its partial sums,
+    // [B, 2B) row j of the panel (workgroup 0 only).  flags[h]: epoch of the
+    // last column workgroup h has published.  Every workgroup reads all
+    // records and sums them in the same order, so all hold identical sums.
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T *smem = (T *)smem_raw;
     const int ldp = chunk + 1;
@@ -86,8 +114,6 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     const int64_t r0 = (int64_t)g * chunk;
     const int rows = (int)((m - r0) < chunk ? (m - r0) : chunk);
     const int nr = (int)(m < B ? m : B);
-    T *res = part + (size_t)PANEL_MAX_WGS * B;
-    int *gen = flags + PANEL_MAX_WGS;
     T *scr = Ps + B * ldp;        // PANEL_THREADS doubles of scratch after the panel
 
     for (int e = tid; e < rows * B; e += PANEL_THREADS) {
@@ -100,6 +126,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     const int cq = tid % B, sub = tid / B;
     for (int j = 0; j < nr; ++j) {
         const int E = epoch0 + j + 1;
+        T *rec = part + (size_t)(j & 1) * PANEL_MAX_WGS * 2 * B;
         // ---- partial sums h_q = sum over local rows i > j of P(i, j) P(i, q), all q:
         // q = j is the squared norm below the diagonal, q > j gives v_j^T P(:, q)
         // and q < j gives Y(:, q)^T v_j (both up to the row-j term and the scale)
@@ -113,40 +140,29 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
                 T s = 0.0;
 #pragma unroll
                 for (int t = 0; t < TPC; ++t) s += scr[tid + t * B];
-                st_coh(&part[(size_t)g * B + tid], s);
+                st_coh(&rec[(size_t)g * 2 * B + tid], s);
+                if (g == 0) st_coh(&rec[B + tid], Ps[tid * ldp + j]);  // row j lives in chunk 0
             }
         }
         mem_drain();
         __syncthreads();
-        if (g != 0) {
-            if (tid == 0) st_coh(&flags[g], E);
-        } else {
-            // workgroup 0 waits for every partial, reduces, and publishes the
-            // sums with row j (which it holds: chunk >= B)
-            if (tid > 0 && tid < G)
-                while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
-            __syncthreads();
+        if (tid == 0) st_coh(&flags[g], E);
+        // ---- wait for every record of this column, then reduce them all
+        if (tid < G)
+            while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
+        __syncthreads();
+        {
             T s = 0.0;
-            for (int h = sub; h < G; h += TPC) s += ld_coh(&part[(size_t)h * B + cq]);
+            for (int h = sub; h < G; h += TPC) s += ld_coh(&rec[(size_t)h * 2 * B + cq]);
             scr[tid] = s;
+            if (tid < B) topsh[tid] = ld_coh(&rec[B + tid]);
             __syncthreads();
             if (tid < B) {
                 T r = 0.0;
 #pragma unroll
                 for (int t = 0; t < TPC; ++t) r += scr[tid + t * B];
-                st_coh(&res[tid], r);
-                st_coh(&res[B + tid], Ps[tid * ldp + j]);
+                hsh[tid] = r;
             }
-            mem_drain();
-            __syncthreads();
-            if (tid == 0) st_coh(gen, E);
-        }
-        if (g != 0 && tid == 0)
-            while (ld_coh(gen) < E) __builtin_amdgcn_s_sleep(1);
-        __syncthreads();
-        if (tid < B) {
-            hsh[tid] = ld_coh(&res[tid]);
-            topsh[tid] = ld_coh(&res[B + tid]);
         }
         __syncthreads();
         // ---- Householder vector of column j: v = (x - beta e_j) / (x_j - beta)
@@ -238,11 +254,16 @@ template <int B, typename T>
 evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
                           T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
 {
-    int maxg = PANEL_MAX_WGS;
+    // about PANEL_WGS workgroups (every one reads every record, so the
+    // traffic per column grows as G^2), more when a chunk would not fit in LDS
+    int maxg = PANEL_WGS;
     if (ctx->panel_wgs > 0 && ctx->panel_wgs < maxg) maxg = (int)ctx->panel_wgs;
     int64_t chunk = evd_ceil_div(m, maxg);
+    const int64_t lds_rows = (140 * 1024 / (int64_t)sizeof(T) - 2 * PANEL_THREADS) / B;
+    if (chunk > lds_rows) chunk = lds_rows;
     if (chunk < B) chunk = B;
     chunk = evd_ceil_div(chunk, 16) * 16;
+    if (evd_ceil_div(m, chunk) > PANEL_MAX_WGS) chunk = evd_ceil_div(evd_ceil_div(m, PANEL_MAX_WGS), 16) * 16;
     int G = (int)evd_ceil_div(m, chunk);
     // LDS: B columns plus one scratch column of PANEL_THREADS doubles
     int64_t ldp = chunk + 1;
@@ -311,7 +332,7 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     t.W = take((size_t)n * b);
     t.M = take((size_t)b * b);
     t.U = take((size_t)2 * nb * b);
-    t.part = take((size_t)PANEL_MAX_WGS * b + 2 * b + 64);
+    t.part = take((size_t)2 * PANEL_MAX_WGS * 2 * b + 64);
     t.Sg = take((size_t)b * b);
     t.taus = take((size_t)b);
     // split-K workspace for the b x b product W^T X and the 2nb x b product
@@ -373,6 +394,15 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
                            dim3(256), 0, s, AB, cnt, (T)0);
     }
     hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(256), 0, s, w.bar, (int64_t)(PANEL_MAX_WGS + 1), 0);
+    // the trailing matrix is kept in full (both triangles) at the start of every
+    // outer block, so A_2 W is a plain product over the stale matrix
+    auto mirror = [&](int64_t i0) {
+        const int64_t m = n - i0;
+        if (m <= 1) return;
+        const dim3 grid((unsigned)evd_ceil_div(m, 32), (unsigned)evd_ceil_div(m, 32));
+        hipLaunchKernelGGL(mirror_lower_kernel<T>, grid, dim3(256), 0, s, m, A + i0 + i0 * lda, lda);
+    };
+    mirror(b);
     const int64_t p = evd_sbr_num_panels(n, b);
     const int64_t q = (ctx->sbr_nb > 0) ? ((ctx->sbr_nb / b) > 0 ? ctx->sbr_nb / b : 1) : w.q;
     const int64_t qmax = w.q < q ? w.q : q;  // the accumulators hold w.q panels
@@ -404,7 +434,7 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
             // W = Y T
             EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)1, Y, ldc, Tk, b, (T)0, w.W, m, (T *)nullptr, 0));
             // X = A_2 W (stale A_2 inside the block) into the Z slot
-            EVD_CHECK(gemm_t(s, OP_S, OP_N, 0, m, b, m, (T)1, A2, lda, w.W, m, (T)0, Zs, ldc, w.gemm_ws,
+            EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, m, (T)1, A2, lda, w.W, m, (T)0, Zs, ldc, w.gemm_ws,
                              w.gemm_ws_elems));
             if (t > 0) {
                 // X -= [Y_J Z_J] ([Z_J Y_J]^T W)
@@ -422,9 +452,11 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
         }
         // A_2 <- A_2 - [Y Z ...] [Z Y ...]^T on the lower triangle, rank 2 qe b
         const int64_t iK = (K0 + qe - 1) * b + b, rK = iK - base, mK = n - iK;
-        if (mK > 0)
+        if (mK > 0) {
             EVD_CHECK(gemm_t(s, OP_N, OP_T, 1, mK, mK, 2 * qe * b, (T)-1, w.YZ + rK, ldc, w.ZY + rK, ldc, (T)1,
                              A + iK + iK * lda, lda, (T *)nullptr, 0));
+            if (K0 + qe < p) mirror(iK + b);  // the next block's trailing matrix
+        }
     }
     {
         dim3 blk(64, 4);
