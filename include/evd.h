@@ -68,8 +68,13 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "timing"       1 = record per-stage times (host-synchronising; for benchmarks)
  *   "panel_wgs"    cap on the workgroups of one panel-QR launch, 0 = automatic
  *   "bcback_valu"  1 = apply the bulge-chasing reflectors one by one on the
- *                  vector ALUs; 0 (default) = in blocks of 32 sweeps on the
- *                  matrix cores (b = 16, 32, 64)
+ *                  vector ALUs; 0 (default) = in compact-WY groups of sweeps on
+ *                  the matrix cores (b = 16, 32, 64)
+ *   "bcback_group" sweeps per group of the blocked BC-back: 0 = automatic
+ *                  (64 for b = 64, else 32), 32 = always 32
+ *   "bcback_rows"  rows of Q per workgroup of the 64-sweep BC-back: 0 =
+ *                  automatic (128 when that still gives every compute unit a
+ *                  workgroup, else 64), 64 or 128
  *   "orgsb_nb"     panels of b columns aggregated into one block reflector in
  *                  SBR-back, in columns (0 = 512)
  *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 256;
@@ -244,11 +249,19 @@ evd_status_t evd_dorgsb_work_size(evd_ctx_t ctx, int64_t n, int64_t b, size_t *b
 evd_status_t evd_dorgsb(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T,
                         double *Q, int64_t ldq, void *work, size_t work_bytes);
 
-/* Stage 4b, BC-back (Sections 2.1.2 and 4.3): Q <- Q H_1 H_2 ... H_m with
- * the bulge-chasing reflectors of evd_dsb2st (rows of Q independent).
- * Q is m_rows x n (ldq >= m_rows). */
-evd_status_t evd_dbcback(evd_ctx_t ctx, int64_t m_rows, int64_t n, int64_t b, const double *V,
-                         const double *TAU, double *Q, int64_t ldq);
+/* Stage 4b, BC-back (Sections 2.1.2 and 4.3): with the bulge-chasing
+ * reflectors H_1 ... H_m of evd_dsb2st (V, TAU as it wrote them),
+ *   trans 'N': Q <- Q H_1 H_2 ... H_m   (Q_d = H_1 ... H_m applied from the right)
+ *   trans 'T': Q <- Q H_m ... H_2 H_1   (= Q Q_d^T: the rows of Q_d^T Z)
+ * Q is m_rows x n, column-major, ldq >= m_rows; rows are independent.
+ * work: device scratch of evd_dbcback_work_size() bytes, 8-byte aligned, for
+ * the T factors of the blocked matrix-core path (reflector groups of 32
+ * sweeps, compact WY; used for b = 16, 32, 64 while "bcback_valu" is 0).  A
+ * size of 0 means the reflector-by-reflector kernel runs and work may be NULL.
+ * Returns EVD_ERR_WORKSPACE if work_bytes is below the queried size. */
+evd_status_t evd_dbcback_work_size(evd_ctx_t ctx, int64_t n, int64_t b, size_t *bytes /*[host]*/);
+evd_status_t evd_dbcback(evd_ctx_t ctx, char trans, int64_t m_rows, int64_t n, int64_t b, const double *V,
+                         const double *TAU, double *Q, int64_t ldq, void *work, size_t work_bytes);
 
 #ifdef __cplusplus
 }

@@ -81,6 +81,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "b")) return &ctx->b;
     if (!strcmp(key, "bc_waves")) return &ctx->bc_waves;
     if (!strcmp(key, "bcback_group")) return &ctx->bcback_group;
+    if (!strcmp(key, "bcback_rows")) return &ctx->bcback_rows;
     if (!strcmp(key, "order")) return &ctx->order;
     if (!strcmp(key, "timing")) return &ctx->timing;
     if (!strcmp(key, "panel_wgs")) return &ctx->panel_wgs;
@@ -101,6 +102,11 @@ evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value)
     int64_t *slot = param_slot(ctx, key);
     if (!slot) { ctx->last_invalid_arg = 2; return EVD_ERR_INVALID_ARG; }
     if (value < 0) { ctx->last_invalid_arg = 3; return EVD_ERR_INVALID_ARG; }
+    if ((slot == &ctx->bcback_group && value != 0 && value != 32 && value != 64) ||
+        (slot == &ctx->bcback_rows && value != 0 && value != 64 && value != 128)) {
+        ctx->last_invalid_arg = 3;
+        return EVD_ERR_INVALID_ARG;
+    }
     *slot = value;
     if (slot == &ctx->last_hip_error && value == 0) evd_tls_hip_error = 0;
     ctx->last_invalid_arg = 0;

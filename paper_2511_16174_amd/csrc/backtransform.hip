@@ -488,24 +488,43 @@ evd_status_t evd_dorgsb(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, in
     return orgsb_run(ctx, n, b, A, lda, T, Q, ldq, work);
 }
 
-evd_status_t evd_dbcback(evd_ctx_t ctx, int64_t m_rows, int64_t n, int64_t b, const double *V, const double *TAU,
-                         double *Q, int64_t ldq)
+evd_status_t evd_dbcback_work_size(evd_ctx_t ctx, int64_t n, int64_t b, size_t *bytes)
+{
+    if (!ctx || !bytes) return EVD_ERR_INVALID_ARG;
+    if (n < 0) { ctx->last_invalid_arg = 2; return EVD_ERR_INVALID_ARG; }
+    if (b < 1 || b > 64 || (64 % b) != 0) { ctx->last_invalid_arg = 3; return EVD_ERR_INVALID_ARG; }
+    *bytes = bcback_mfma_t_elems(n, b) * sizeof(double);
+    return EVD_OK;
+}
+
+evd_status_t evd_dbcback(evd_ctx_t ctx, char trans, int64_t m_rows, int64_t n, int64_t b, const double *V,
+                         const double *TAU, double *Q, int64_t ldq, void *work, size_t work_bytes)
 {
     if (!ctx) return EVD_ERR_INVALID_ARG;
+    const bool rev = (trans == 'T' || trans == 't');
+    const size_t need = ctx->bcback_valu ? 0 : bcback_mfma_t_elems(n > 0 ? n : 0, b) * sizeof(double);
     int bad = 0;
-    if (m_rows < 0) bad = 2;
-    else if (n < 0) bad = 3;
-    else if (b < 1 || b > 64 || (64 % b) != 0) bad = 4;
-    else if (n > 2 && !V) bad = 5;
-    else if (n > 2 && !TAU) bad = 6;
-    else if (m_rows > 0 && n > 0 && !Q) bad = 7;
-    else if (ldq < (m_rows > 1 ? m_rows : 1)) bad = 8;
+    if (!(rev || trans == 'N' || trans == 'n')) bad = 2;
+    else if (m_rows < 0) bad = 3;
+    else if (n < 0) bad = 4;
+    else if (b < 1 || b > 64 || (64 % b) != 0) bad = 5;
+    else if (n > 2 && !V) bad = 6;
+    else if (n > 2 && !TAU) bad = 7;
+    else if (m_rows > 0 && n > 0 && !Q) bad = 8;
+    else if (ldq < (m_rows > 1 ? m_rows : 1)) bad = 9;
+    else if (need && m_rows > 0 && !work) bad = 10;
+    else if (m_rows > 0 && work_bytes < need) bad = 11;
     ctx->last_invalid_arg = bad;
-    if (bad) return EVD_ERR_INVALID_ARG;
+    if (bad) return bad == 11 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n < 3 || m_rows == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
     EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
-    return bcback_run(ctx, m_rows, n, b, V, TAU, Q, ldq);
+    if (need && bcback_mfma_fits(ldq)) {
+        double *Tg = (double *)work;
+        EVD_CHECK(bcback_mfma_prepare(ctx, n, b, V, TAU, Tg, rev));
+        return bcback_mfma_apply(ctx, m_rows, n, b, V, Q, ldq, Tg, rev);
+    }
+    return rev ? bcback_run_rev(ctx, m_rows, n, b, V, TAU, Q, ldq) : bcback_run(ctx, m_rows, n, b, V, TAU, Q, ldq);
 }
 
 }  // extern "C"

@@ -6,8 +6,8 @@
 // (column j of Y holds v_j shifted down by j) and T is upper triangular
 // (forward column recurrence).  Applying a group to a block of rows of Q is
 // three small products on v_mfma_f64_16x16x4:
-//   P = Q_w Y (16 x 32),  P2 = P T (P T^T for the reverse order),
-//   Q_w <- Q_w - P2 Y^T,
+//   P = Q_w Y (16 x 32),  P2 = P (-T) (P (-T)^T for the reverse order),
+//   Q_w <- Q_w + P2 Y^T,
 // skipping the zero 16 x 4 blocks of the staircase and of T.  The groups are
 // taken in the same order as the reflector-by-reflector kernel (blocks
 // ascending, steps descending; everything reversed for the reverse product),
@@ -19,12 +19,26 @@
 //
 // T factors are computed for all groups beforehand by bct_kernel (one
 // wavefront per group: Gram matrix of the staircase, then the recurrence
-// T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T v_j), T[j, j] = tau_j).
+// T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T v_j), T[j, j] = tau_j) and
+// stored negated, so that every product accumulates with a plus sign.
+// Global addresses are a wave-uniform 64-bit base plus one 32-bit lane offset,
+// and a step whose columns and rows are all in range skips the bounds tests.
 #include "common.h"
 
 namespace {
 
 constexpr int BC_G = 32;   // sweeps per group
+
+template <typename P>
+__device__ __forceinline__ P &at(P *base, uint32_t byte_off)
+{
+    return *(P *)((char *)base + byte_off);
+}
+template <typename P>
+__device__ __forceinline__ const P &at(const P *base, uint32_t byte_off)
+{
+    return *(const P *)((const char *)base + byte_off);
+}
 
 __global__ __launch_bounds__(64) void bct_kernel(int64_t n, int B, const double *__restrict__ V,
                                                  const double *__restrict__ TAU, double *__restrict__ Tg, int64_t nblk)
@@ -75,7 +89,7 @@ __global__ __launch_bounds__(64) void bct_kernel(int64_t n, int B, const double 
         __syncthreads();
     }
     double *T = Tg + (s * nblk + blk) * (int64_t)(G * G);
-    for (int e = tid; e < G * G; e += 64) T[e] = tsh[e / G][e % G];  // row-major [k][j]
+    for (int e = tid; e < G * G; e += 64) T[e] = -tsh[e / G][e % G];  // -T, row-major [k][j]
 }
 
 template <int B, bool REV>
@@ -95,11 +109,17 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
     __shared__ double Ts[2][G][LDT];
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: lets row0 live in scalar registers
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + li;
-    const bool rowok = row < mrows;
-    double *Qr = Q + row;
+    // Addresses: a wave-uniform base (scalar registers, one per k-step) plus
+    // one 32-bit lane byte offset (16 rows x 4 columns).
+    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const bool rows_full = row0 + 16 <= mrows;
+    const bool rowok = row0 + li < mrows;
+    double *Qw = Q + row0;
+    const int64_t ldq4 = 4 * ldq;                                          // doubles per k-step
+    const uint32_t loff = ((uint32_t)li + (uint32_t)lk * (uint32_t)ldq) * 8u;  // lane offset in bytes
     const int64_t nsweeps = n - 2;
     const int64_t nsteps = bc_num_steps(n, B);
 
@@ -109,16 +129,22 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
 
     // a group's operands are fetched into registers before the current group
     // is applied and written to LDS after it, so the fetch latency overlaps
-    // the matrix-core work
+    // the matrix-core work.  The vectors of sweeps c0 .. c0 + G - 1 at step s
+    // are G B consecutive doubles of V.
     constexpr int NV = G * B / 256, NT = G * G / 256;
     double gv[NV], gt[NT];
     auto fetch_group = [&](int64_t blk, int64_t s) {
         const int64_t c0 = blk * G;
+        const double *Vg = V + (s * n + c0) * B;
+        if (c0 + G <= nsweeps && s < nsteps) {
 #pragma unroll
-        for (int r = 0; r < NV; ++r) {
-            const int e = tid + r * 256, j = e / B, i = e % B;
-            const int64_t c = c0 + j;
-            gv[r] = (c < nsweeps && s < nsteps) ? V[((s * n) + c) * B + i] : 0.0;
+            for (int r = 0; r < NV; ++r) gv[r] = Vg[tid + r * 256];
+        } else {
+#pragma unroll
+            for (int r = 0; r < NV; ++r) {
+                const int e = tid + r * 256;
+                gv[r] = (c0 + e / B < nsweeps && s < nsteps) ? Vg[e] : 0.0;
+            }
         }
         const double *T = Tg + (s * nblk + blk) * (int64_t)(G * G);
 #pragma unroll
@@ -136,7 +162,6 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
             Ts[buf][e / G][e % G] = gt[r];
         }
     };
-
     double x[KW];
     double pre[SHK];
     const int64_t blk_first = REV ? nblk - 1 : 0;
@@ -146,10 +171,18 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
         const int64_t S = rem < 0 ? 0 : rem / B + 1;
         if (S == 0) continue;
         int64_t base = REV ? c0 + 1 : c0 + 1 + (S - 1) * B;
+        {
+            const double *Qc = Qw + base * ldq;
+            if (rows_full && base + W <= n) {
 #pragma unroll
-        for (int kk = 0; kk < KW; ++kk) {
-            const int64_t col = base + 4 * kk + lk;
-            x[kk] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
+                for (int kk = 0; kk < KW; ++kk) x[kk] = at(Qc + kk * ldq4, loff);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KW; ++kk) {
+                    const int64_t col = base + 4 * kk + lk;
+                    x[kk] = (rowok && col < n) ? at(Qc + kk * ldq4, loff) : 0.0;
+                }
+            }
         }
         __syncthreads();
         fetch_group(blk, REV ? 0 : S - 1);
@@ -159,32 +192,54 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
         for (int64_t it = 0; it < S; ++it) {
             const int64_t s = REV ? it : S - 1 - it;
             const bool more = it + 1 < S;
+            // every column the step reads, writes or prefetches is below n
+            const bool full = rows_full && base + W + B <= n;
             if (more) {
+                const int64_t pcol = REV ? base + W : base - B;
+                const double *Qc = Qw + pcol * ldq;
+                if (full) {
 #pragma unroll
-                for (int k = 0; k < SHK; ++k) {
-                    const int64_t col = REV ? base + B + 4 * (KW - SHK + k) + lk : base - B + 4 * k + lk;
-                    pre[k] = (rowok && col < n) ? Qr[col * ldq] : 0.0;
+                    for (int k = 0; k < SHK; ++k) pre[k] = at(Qc + k * ldq4, loff);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < SHK; ++k) {
+                        const int64_t col = pcol + 4 * k + lk;
+                        pre[k] = (rowok && col < n) ? at(Qc + k * ldq4, loff) : 0.0;
+                    }
                 }
                 fetch_group(blk, REV ? s + 1 : s - 1);
             }
-            // P = Q_w Y: reflector tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3
-            double4_t P[2];
+            // The three products are written k-step outer, output tile inner,
+            // so that consecutive matrix-core instructions are independent.
+            // P = Q_w Y: reflector tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3;
+            // even and odd k-steps go to separate accumulators.
+            double4_t P[2], Po[2];
 #pragma unroll
             for (int jt = 0; jt < 2; ++jt) {
                 P[jt] = (double4_t){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kk = 4 * jt; kk < 4 * jt + SHK + 4; ++kk)
-                    if (kk < KW)
-                        P[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ys[buf][4 * kk + lk][16 * jt + li], x[kk], P[jt], 0,
-                                                                     0, 0);
+                Po[jt] = (double4_t){0.0, 0.0, 0.0, 0.0};
             }
-            // P2 = P T (upper) or P T^T (REV)
+#pragma unroll
+            for (int kk = 0; kk < KW; ++kk) {
+#pragma unroll
+                for (int jt = 0; jt < 2; ++jt) {
+                    if (kk >= 4 * jt && kk < 4 * jt + SHK + 4) {
+                        const double a = Ys[buf][4 * kk + lk][16 * jt + li];
+                        if (kk & 1) Po[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x[kk], Po[jt], 0, 0, 0);
+                        else P[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x[kk], P[jt], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int jt = 0; jt < 2; ++jt) P[jt] += Po[jt];
+            // P2 = P (-T) (upper) or P (-T)^T (REV); the stored factors are -T
             double4_t P2[2];
 #pragma unroll
-            for (int jt = 0; jt < 2; ++jt) {
-                P2[jt] = (double4_t){0.0, 0.0, 0.0, 0.0};
+            for (int jt = 0; jt < 2; ++jt) P2[jt] = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
+            for (int kk = 0; kk < 8; ++kk) {
+#pragma unroll
+                for (int jt = 0; jt < 2; ++jt) {
                     const bool nz = REV ? (kk >= 4 * jt) : (kk <= 4 * jt + 3);
                     if (nz) {
                         const double a = REV ? Ts[buf][16 * jt + li][4 * kk + lk] : Ts[buf][4 * kk + lk][16 * jt + li];
@@ -192,29 +247,41 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
                     }
                 }
             }
-            // Q_w -= P2 Y^T: window tile t meets reflectors 16 t - (B - 1) .. 16 t + 15
+            // Q_w += P2 Y^T: window tile t meets reflectors 16 t - (B - 1) .. 16 t + 15
+            double4_t acc[KW / 4];
 #pragma unroll
-            for (int t = 0; t < KW / 4; ++t) {
-                double4_t acc = (double4_t){x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]};
+            for (int t = 0; t < KW / 4; ++t) acc[t] = (double4_t){x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]};
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
+            for (int kk = 0; kk < 8; ++kk) {
+#pragma unroll
+                for (int t = 0; t < KW / 4; ++t) {
                     const int jlo = 4 * kk, jhi = 4 * kk + 3;
                     if (jhi >= 16 * t - (B - 1) && jlo <= 16 * t + 15)
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Ys[buf][16 * t + li][4 * kk + lk], P2[kk / 4][kk % 4],
-                                                                   acc, 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ys[buf][16 * t + li][4 * kk + lk],
+                                                                      P2[kk / 4][kk % 4], acc[t], 0, 0, 0);
                 }
-                x[4 * t] = acc[0];
-                x[4 * t + 1] = acc[1];
-                x[4 * t + 2] = acc[2];
-                x[4 * t + 3] = acc[3];
+            }
+#pragma unroll
+            for (int t = 0; t < KW / 4; ++t) {
+                x[4 * t] = acc[t][0];
+                x[4 * t + 1] = acc[t][1];
+                x[4 * t + 2] = acc[t][2];
+                x[4 * t + 3] = acc[t][3];
             }
             if (more) {
                 store_group(buf ^ 1);
                 if (REV) {
+                    // the first B columns leave the window
+                    double *Qc = Qw + base * ldq;
+                    if (full) {
 #pragma unroll
-                    for (int kk = 0; kk < SHK; ++kk) {
-                        const int64_t col = base + 4 * kk + lk;
-                        if (rowok && col < n) Qr[col * ldq] = x[kk];
+                        for (int kk = 0; kk < SHK; ++kk) at(Qc + kk * ldq4, loff) = x[kk];
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < SHK; ++kk) {
+                            const int64_t col = base + 4 * kk + lk;
+                            if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[kk];
+                        }
                     }
 #pragma unroll
                     for (int kk = 0; kk < KW - SHK; ++kk) x[kk] = x[kk + SHK];
@@ -222,10 +289,17 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
                     for (int k = 0; k < SHK; ++k) x[KW - SHK + k] = pre[k];
                     base += B;
                 } else {
+                    // the last B columns leave the window
+                    double *Qc = Qw + (base + W - B) * ldq;
+                    if (full) {
 #pragma unroll
-                    for (int kk = KW - SHK; kk < KW; ++kk) {
-                        const int64_t col = base + 4 * kk + lk;
-                        if (rowok && col < n) Qr[col * ldq] = x[kk];
+                        for (int kk = 0; kk < SHK; ++kk) at(Qc + kk * ldq4, loff) = x[KW - SHK + kk];
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < SHK; ++kk) {
+                            const int64_t col = base + W - B + 4 * kk + lk;
+                            if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[KW - SHK + kk];
+                        }
                     }
 #pragma unroll
                     for (int kk = KW - 1; kk >= SHK; --kk) x[kk] = x[kk - SHK];
@@ -237,42 +311,400 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
             __syncthreads();
             buf ^= 1;
         }
+        {
+            double *Qc = Qw + base * ldq;
+            if (rows_full && base + W <= n) {
 #pragma unroll
-        for (int kk = 0; kk < KW; ++kk) {
-            const int64_t col = base + 4 * kk + lk;
-            if (rowok && col < n) Qr[col * ldq] = x[kk];
+                for (int kk = 0; kk < KW; ++kk) at(Qc + kk * ldq4, loff) = x[kk];
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KW; ++kk) {
+                    const int64_t col = base + 4 * kk + lk;
+                    if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[kk];
+                }
+            }
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Wide groups for b = 64: GW = 64 sweeps per group.  The window slides by b
+// columns per step whatever the group size, so the rows of Q streamed through
+// HBM per unit of reflector work halve against 32-sweep groups (the 32-sweep
+// kernel is bound by exactly that stream).  LDS holds the group's vectors
+// packed, one padded row per sweep (16 zeros between rows, so the staircase
+// reads Y(r, c) = v_c[r - c] fall on zeros outside 0 <= r - c < b without
+// masking), and -T (or -T^T for the reverse order) as its nonzero 16 x 4
+// tiles, each stored in the lane order of the matrix-core operand.
+constexpr int BC_GW = 64;
+
+template <int G>
+__host__ __device__ constexpr int wide_tiles() { return (G / 16) * (G / 4) - 2 * (G / 16) * (G / 16 - 1); }
+
+// position of tile (jt, kk) among the nonzero tiles of M = -T (upper: kk <= 4 jt + 3)
+// or M = -T^T (REV, lower: kk >= 4 jt), jt outer
+template <int G, bool REV>
+__host__ __device__ constexpr int wide_tile(int jt, int kk)
+{
+    return REV ? jt * (G / 4) - 2 * jt * (jt - 1) + kk - 4 * jt : 2 * jt * (jt + 1) + kk;
+}
+
+// -T (or -T^T) of every wide group in tile order: tile (jt, kk), lane l holds
+// M(4 kk + l / 16, 16 jt + l % 16).  One workgroup per group.
+template <int G, bool REV>
+__global__ __launch_bounds__(256) void bct_wide_kernel(int64_t n, int B, const double *__restrict__ V,
+                                                       const double *__restrict__ TAU, double *__restrict__ Tg,
+                                                       int64_t nblk)
+{
+    constexpr int NTT = wide_tiles<G>();
+    __shared__ double vsh[G][65];
+    __shared__ double gsh[G][G + 1];
+    __shared__ double tsh[G][G + 1];
+    __shared__ double tau[G];
+    const int64_t blk = blockIdx.x, s = blockIdx.y;
+    const int64_t nsweeps = n - 2, nsteps = bc_num_steps(n, B);
+    const int tid = threadIdx.x;
+    {
+        const int64_t rem = n - 1 - (blk * G + 1);
+        const int64_t S = rem < 0 ? 0 : rem / B + 1;
+        if (s >= S) return;
+    }
+    for (int e = tid; e < G * B; e += 256) {
+        const int j = e / B, i = e % B;
+        const int64_t c = blk * G + j;
+        vsh[j][i] = (c < nsweeps && s < nsteps) ? V[((s * n) + c) * B + i] : 0.0;
+    }
+    for (int j = tid; j < G; j += 256) {
+        const int64_t c = blk * G + j;
+        tau[j] = (c < nsweeps && s < nsteps) ? TAU[s * n + c] : 0.0;
+    }
+    for (int e = tid; e < G * (G + 1); e += 256) (&tsh[0][0])[e] = 0.0;
+    __syncthreads();
+    for (int e = tid; e < G * G; e += 256) {
+        const int i = e / G, j = e % G;
+        if (i < j) {
+            const int d = j - i;
+            double acc = 0.0;
+            for (int t = 0; t + d < B; ++t) acc += vsh[i][t + d] * vsh[j][t];
+            gsh[i][j] = acc;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < G; ++j) {
+        if (tid < j) {
+            double acc = 0.0;
+            for (int k = tid; k < j; ++k) acc += tsh[tid][k] * gsh[k][j];
+            tsh[tid][j] = -tau[j] * acc;
+        }
+        if (tid == 0) tsh[j][j] = tau[j];
+        __syncthreads();
+    }
+    double *T = Tg + (s * nblk + blk) * (int64_t)(NTT * 64);
+    for (int jt = 0; jt < G / 16; ++jt) {
+        const int k0 = REV ? 4 * jt : 0, k1 = REV ? G / 4 : 4 * jt + 4;
+        for (int e = tid; e < (k1 - k0) * 64; e += 256) {
+            const int kk = k0 + e / 64, l = e % 64;
+            const int r = 4 * kk + l / 16, c = 16 * jt + l % 16;  // M(r, c)
+            T[wide_tile<G, REV>(jt, kk) * 64 + l] = REV ? -tsh[c][r] : -tsh[r][c];
+        }
+    }
+}
+
+template <int B, int G, int NWV, bool REV>
+__global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows, int64_t n,
+                                                                  const double *__restrict__ V,
+                                                                  const double *__restrict__ Tg, int64_t nblk,
+                                                                  double *__restrict__ Q, int64_t ldq)
+{
+    constexpr int W = G + B;      // window columns
+    constexpr int KW = W / 4;     // k-steps over the window
+    constexpr int SHK = B / 4;    // k-steps the window slides per step
+    constexpr int JT = G / 16;    // reflector tiles
+    constexpr int GK = G / 4;     // k-steps over the reflectors
+    constexpr int WT = W / 16;    // window tiles
+    constexpr int LDV = B + 16;   // padded row of one sweep's vector
+    constexpr int VPAD = 16;
+    constexpr int VS = VPAD + G * LDV;
+    constexpr int NTT = wide_tiles<G>();
+    constexpr int TS = NTT * 64;
+    constexpr int NTH = NWV * 64;
+    constexpr int NV = G * B / NTH, NT = TS / NTH;
+    static_assert(W % 16 == 0 && (G * B) % NTH == 0 && TS % NTH == 0, "tile shapes");
+    __shared__ double Vs[2][VS];
+    __shared__ double Ts[2][TS];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * (16 * NWV) + wave * 16;
+    const bool rows_full = row0 + 16 <= mrows;
+    const bool rowok = row0 + li < mrows;
+    double *Qw = Q + row0;
+    const int64_t ldq4 = 4 * ldq;
+    const uint32_t loff = ((uint32_t)li + (uint32_t)lk * (uint32_t)ldq) * 8u;
+    const int64_t nsweeps = n - 2;
+
+    for (int e = tid; e < 2 * VS; e += NTH) (&Vs[0][0])[e] = 0.0;
+    __syncthreads();
+
+    double gv[NV], gt[NT];
+    auto fetch_group = [&](int64_t blk, int64_t s) {
+        const int64_t c0 = blk * G;
+        const double *Vg = V + (s * n + c0) * B;
+        if (c0 + G <= nsweeps) {
+#pragma unroll
+            for (int r = 0; r < NV; ++r) gv[r] = Vg[tid + r * NTH];
+        } else {
+#pragma unroll
+            for (int r = 0; r < NV; ++r) {
+                const int e = tid + r * NTH;
+                gv[r] = (c0 + e / B < nsweeps) ? Vg[e] : 0.0;
+            }
+        }
+        const double *T = Tg + (s * nblk + blk) * (int64_t)TS;
+#pragma unroll
+        for (int r = 0; r < NT; ++r) gt[r] = T[tid + r * NTH];
+    };
+    auto store_group = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+            const int e = tid + r * NTH, j = e / B, i = e % B;
+            Vs[buf][VPAD + j * LDV + i] = gv[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NT; ++r) Ts[buf][tid + r * NTH] = gt[r];
+    };
+    // Y(r, c) of the group in buffer buf: window row r, reflector c
+    auto yv = [&](int buf, int r, int c) -> double { return Vs[buf][VPAD + c * LDV + (r - c)]; };
+
+    double x[KW];
+    double pre[SHK];
+    const int64_t blk_first = REV ? nblk - 1 : 0;
+    for (int64_t blk = blk_first; REV ? blk >= 0 : blk < nblk; blk += REV ? -1 : 1) {
+        const int64_t c0 = blk * G;
+        const int64_t rem = n - 1 - (c0 + 1);
+        const int64_t S = rem < 0 ? 0 : rem / B + 1;
+        if (S == 0) continue;
+        int64_t base = REV ? c0 + 1 : c0 + 1 + (S - 1) * B;
+        {
+            const double *Qc = Qw + base * ldq;
+            if (rows_full && base + W <= n) {
+#pragma unroll
+                for (int kk = 0; kk < KW; ++kk, Qc += ldq4) x[kk] = at(Qc, loff);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KW; ++kk) {
+                    const int64_t col = base + 4 * kk + lk;
+                    x[kk] = (rowok && col < n) ? at(Qc + kk * ldq4, loff) : 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        fetch_group(blk, REV ? 0 : S - 1);
+        store_group(0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t it = 0; it < S; ++it) {
+            const int64_t s = REV ? it : S - 1 - it;
+            const bool more = it + 1 < S;
+            const bool full = rows_full && base + W + B <= n;
+            if (more) {
+                const int64_t pcol = REV ? base + W : base - B;
+                const double *Qc = Qw + pcol * ldq;
+                if (full) {
+#pragma unroll
+                    for (int k = 0; k < SHK; ++k, Qc += ldq4) pre[k] = at(Qc, loff);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < SHK; ++k) {
+                        const int64_t col = pcol + 4 * k + lk;
+                        pre[k] = (rowok && col < n) ? at(Qc + k * ldq4, loff) : 0.0;
+                    }
+                }
+            }
+            // P = Q_w Y: reflector tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3
+            double4_t P[JT];
+#pragma unroll
+            for (int jt = 0; jt < JT; ++jt) P[jt] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KW; ++kk) {
+#pragma unroll
+                for (int jt = 0; jt < JT; ++jt) {
+                    if (kk >= 4 * jt && kk < 4 * jt + SHK + 4)
+                        P[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 4 * kk + lk, 16 * jt + li), x[kk], P[jt],
+                                                                     0, 0, 0);
+                }
+            }
+            // P2 = P M, M = -T (upper) or -T^T (REV), from the stored tiles
+            double4_t P2[JT];
+#pragma unroll
+            for (int jt = 0; jt < JT; ++jt) P2[jt] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < GK; ++kk) {
+#pragma unroll
+                for (int jt = 0; jt < JT; ++jt) {
+                    const bool nz = REV ? (kk >= 4 * jt) : (kk <= 4 * jt + 3);
+                    if (nz)
+                        P2[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[buf][wide_tile<G, REV>(jt, kk) * 64 + lane],
+                                                                      P[kk / 4][kk % 4], P2[jt], 0, 0, 0);
+                }
+            }
+            // the next group's operands are fetched once P is dead (register
+            // pressure) and land during the third product
+            if (more) fetch_group(blk, REV ? s + 1 : s - 1);
+            // Q_w += P2 Y^T: window tile t meets reflectors 16 t - (B - 1) .. 16 t + 15
+            double4_t acc[WT];
+#pragma unroll
+            for (int t = 0; t < WT; ++t) acc[t] = (double4_t){x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]};
+#pragma unroll
+            for (int kk = 0; kk < GK; ++kk) {
+#pragma unroll
+                for (int t = 0; t < WT; ++t) {
+                    if (4 * kk + 3 >= 16 * t - (B - 1) && 4 * kk <= 16 * t + 15)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 16 * t + li, 4 * kk + lk),
+                                                                      P2[kk / 4][kk % 4], acc[t], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < WT; ++t) {
+                x[4 * t] = acc[t][0];
+                x[4 * t + 1] = acc[t][1];
+                x[4 * t + 2] = acc[t][2];
+                x[4 * t + 3] = acc[t][3];
+            }
+            if (more) {
+                store_group(buf ^ 1);
+                if (REV) {
+                    double *Qc = Qw + base * ldq;
+                    if (full) {
+#pragma unroll
+                        for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[kk];
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < SHK; ++kk) {
+                            const int64_t col = base + 4 * kk + lk;
+                            if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[kk];
+                        }
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < KW - SHK; ++kk) x[kk] = x[kk + SHK];
+#pragma unroll
+                    for (int k = 0; k < SHK; ++k) x[KW - SHK + k] = pre[k];
+                    base += B;
+                } else {
+                    double *Qc = Qw + (base + W - B) * ldq;
+                    if (full) {
+#pragma unroll
+                        for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[KW - SHK + kk];
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < SHK; ++kk) {
+                            const int64_t col = base + W - B + 4 * kk + lk;
+                            if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[KW - SHK + kk];
+                        }
+                    }
+#pragma unroll
+                    for (int kk = KW - 1; kk >= SHK; --kk) x[kk] = x[kk - SHK];
+#pragma unroll
+                    for (int k = 0; k < SHK; ++k) x[k] = pre[k];
+                    base -= B;
+                }
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+        {
+            double *Qc = Qw + base * ldq;
+            if (rows_full && base + W <= n) {
+#pragma unroll
+                for (int kk = 0; kk < KW; ++kk, Qc += ldq4) at(Qc, loff) = x[kk];
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KW; ++kk) {
+                    const int64_t col = base + 4 * kk + lk;
+                    if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[kk];
+                }
+            }
         }
     }
 }
 
 }  // namespace
 
-int64_t bcback_mfma_nblk(int64_t n) { return n > 2 ? evd_ceil_div(n - 2, BC_G) : 0; }
+namespace {
 
-// T workspace of the blocked BC-back (doubles); 0 when the blocked kernel
-// does not apply to b.
+int64_t group_count(int64_t n, int g) { return n > 2 ? evd_ceil_div(n - 2, (int64_t)g) : 0; }
+
+// sweeps per group: 64 for b = 64 unless "bcback_group" asks for 32
+int group_sweeps(evd_ctx_t ctx, int64_t b) { return (b == 64 && ctx->bcback_group != 32) ? BC_GW : BC_G; }
+
+size_t t_elems_for(int64_t n, int64_t b, int g)
+{
+    const size_t per = (g == BC_GW) ? (size_t)wide_tiles<BC_GW>() * 64 : (size_t)BC_G * BC_G;
+    return (size_t)bc_num_steps(n, b) * (size_t)group_count(n, g) * per;
+}
+
+}  // namespace
+
+// T workspace of the blocked BC-back (doubles, enough for either group size);
+// 0 when the blocked kernels do not apply to b.
 size_t bcback_mfma_t_elems(int64_t n, int64_t b)
 {
     if (!(b == 16 || b == 32 || b == 64) || n < 3) return 0;
-    return (size_t)bc_num_steps(n, b) * (size_t)bcback_mfma_nblk(n) * BC_G * BC_G;
+    const size_t t32 = t_elems_for(n, b, BC_G);
+    const size_t t64 = (b == 64) ? t_elems_for(n, b, BC_GW) : 0;
+    return t32 > t64 ? t32 : t64;
 }
 
-// Q (mrows x n) <- Q H_1 ... H_m (rev = false) or Q H_m ... H_1 (rev = true);
-// Tg holds bcback_mfma_t_elems(n, b) doubles of scratch.
-evd_status_t bcback_mfma_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
-                             double *Q, int64_t ldq, double *Tg, bool rev)
+// T factors of every group into Tg (bcback_mfma_t_elems(n, b) doubles), laid
+// out for the order (rev) that bcback_mfma_apply will use.
+evd_status_t bcback_mfma_prepare(evd_ctx_t ctx, int64_t n, int64_t b, const double *V, const double *TAU, double *Tg,
+                                 bool rev)
+{
+    if (n < 3) return EVD_OK;
+    const int g = group_sweeps(ctx, b);
+    const int64_t nblk = group_count(n, g);
+    const int64_t nsteps = bc_num_steps(n, b);
+    const dim3 grid((unsigned)nblk, (unsigned)nsteps);
+    if (g == BC_GW) {
+        if (rev) hipLaunchKernelGGL((bct_wide_kernel<BC_GW, true>), grid, dim3(256), 0, ctx->stream, n, (int)b, V, TAU,
+                                    Tg, nblk);
+        else hipLaunchKernelGGL((bct_wide_kernel<BC_GW, false>), grid, dim3(256), 0, ctx->stream, n, (int)b, V, TAU,
+                                Tg, nblk);
+    } else {
+        hipLaunchKernelGGL(bct_kernel, grid, dim3(64), 0, ctx->stream, n, (int)b, V, TAU, Tg, nblk);
+    }
+    return evd_check_last();
+}
+
+// Q (mrows x n) <- Q H_1 ... H_m (rev = false) or Q H_m ... H_1 (rev = true),
+// with the T factors from bcback_mfma_prepare (same b, rev and group size).
+evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, double *Q,
+                               int64_t ldq, const double *Tg, bool rev)
 {
     hipStream_t s = ctx->stream;
     if (n < 3 || mrows <= 0) return EVD_OK;
-    const int64_t nblk = bcback_mfma_nblk(n);
-    const int64_t nsteps = bc_num_steps(n, b);
-    hipLaunchKernelGGL(bct_kernel, dim3((unsigned)nblk, (unsigned)nsteps), dim3(64), 0, s, n, (int)b, V, TAU, Tg, nblk);
+    if (!bcback_mfma_fits(ldq)) return EVD_ERR_INVALID_ARG;  // lane offsets are 32-bit byte offsets
+    const int g = group_sweeps(ctx, b);
+    const int64_t nblk = group_count(n, g);
+    if (g == BC_GW) {
+        // 128-row workgroups (two wavefronts per SIMD) when they still fill
+        // every compute unit, else 64-row ones
+        const bool w8 = ctx->bcback_rows ? ctx->bcback_rows == 128 : mrows >= (int64_t)128 * ctx->num_cus;
+        const dim3 grid((unsigned)evd_ceil_div(mrows, w8 ? 128 : 64));
+#define EVD_BCW(NW, RV)                                                                                               hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, NW, RV>), grid, dim3(NW * 64), 0, s, mrows, n, V, Tg, nblk, Q,                        ldq);
+        if (w8) {
+            if (rev) { EVD_BCW(8, true) } else { EVD_BCW(8, false) }
+        } else {
+            if (rev) { EVD_BCW(4, true) } else { EVD_BCW(4, false) }
+        }
+#undef EVD_BCW
+        return evd_check_last();
+    }
     const dim3 grid((unsigned)evd_ceil_div(mrows, 64)), blk(256);
-#define EVD_BCM(BB)                                                                                               \
-    if (rev) hipLaunchKernelGGL((bcback_mfma_kernel<BB, true>), grid, blk, 0, s, mrows, n, V, (const double *)Tg,  \
-                                nblk, Q, ldq);                                                                     \
-    else hipLaunchKernelGGL((bcback_mfma_kernel<BB, false>), grid, blk, 0, s, mrows, n, V, (const double *)Tg, nblk, \
-                            Q, ldq);
+#define EVD_BCM(BB)                                                                                                   if (rev) hipLaunchKernelGGL((bcback_mfma_kernel<BB, true>), grid, blk, 0, s, mrows, n, V, (const double *)Tg,                                  nblk, Q, ldq);                                                                         else hipLaunchKernelGGL((bcback_mfma_kernel<BB, false>), grid, blk, 0, s, mrows, n, V, (const double *)Tg, nblk,                             Q, ldq);
     switch (b) {
     case 16: EVD_BCM(16) break;
     case 32: EVD_BCM(32) break;

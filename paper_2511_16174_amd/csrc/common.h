@@ -151,7 +151,8 @@ struct evd_ctx_s {
     // tunables
     int64_t b;                // band width (0 = auto)
     int64_t bc_waves;         // persistent BC waves (0 = auto)
-    int64_t bcback_group;     // sweeps per BC-back group (0 = auto)
+    int64_t bcback_group;     // sweeps per blocked BC-back group (0 = auto: 64 for b = 64, else 32)
+    int64_t bcback_rows;      // rows per workgroup of the 64-sweep BC-back kernel (0 = auto, 64, 128)
     int64_t order;            // 0 = reordered stages (paper), 1 = conventional
     int64_t timing;           // 1 = record per-stage times
     int num_cus;
@@ -241,6 +242,16 @@ struct GemmProblem {
     int64_t m, n, k;
 };
 evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob, int64_t max_m, int64_t max_n);
+
+// Blocked BC-back on the matrix cores (b in {16, 32, 64}): T factors of the
+// reflector groups (bcback_mfma_t_elems doubles, 0 for other b), then
+// Q <- Q H_1 ... H_m (rev false) or Q H_m ... H_1 (rev true).
+size_t bcback_mfma_t_elems(int64_t n, int64_t b);
+inline bool bcback_mfma_fits(int64_t ldq) { return ldq > 0 && ldq <= ((int64_t)1 << 27); }  // 3 ldq + 15 doubles in a 32-bit byte offset
+evd_status_t bcback_mfma_prepare(evd_ctx_t ctx, int64_t n, int64_t b, const double *V, const double *TAU, double *Tg,
+                                 bool rev);
+evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, double *Q,
+                               int64_t ldq, const double *Tg, bool rev);
 
 // One K-slice of a GEMM operand tile is an LC x LS block in memory (LC
 // contiguous elements, lines ld apart).  Thread tid loads elements

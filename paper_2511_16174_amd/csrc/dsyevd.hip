@@ -31,9 +31,6 @@ evd_status_t bcback_run_rev(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, 
 evd_status_t ormsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *C,
                        int64_t ldc, void *work);
 evd_status_t transpose_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *B, int64_t ldb);
-size_t bcback_mfma_t_elems(int64_t n, int64_t b);
-evd_status_t bcback_mfma_run(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, const double *TAU,
-                             double *Q, int64_t ldq, double *Tg, bool rev);
 
 namespace {
 
@@ -177,9 +174,11 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
         if (ctx->order == 0) {
             // reordered stages (Section 3.3): Q_sb = Q_s H_1 ... H_m, then Q = Q_sb Q_d
             EVD_CHECK(orgsb_run(ctx, n, b, A, lda, w.T, w.Qs, n, w.orgsb));
+            const bool blocked = w.Tg && ctx->bcback_valu == 0 && bcback_mfma_fits(n);
+            if (blocked) EVD_CHECK(bcback_mfma_prepare(ctx, n, b, w.V, w.TAU, w.Tg, false));
             mark(4);
-            if (w.Tg && ctx->bcback_valu == 0)
-                EVD_CHECK(bcback_mfma_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n, w.Tg, false));
+            if (blocked)
+                EVD_CHECK(bcback_mfma_apply(ctx, n, n, b, w.V, w.Qs, n, w.Tg, false));
             else
                 EVD_CHECK(bcback_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n));
             mark(5);
@@ -188,11 +187,14 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
         } else {
             // conventional order: Z = H_1 ... H_m Q_d as rows of Z^T = Q_d^T H_m ... H_1,
             // then Q = Q_s Z (the panel reflectors still live in A's panel columns)
-            // stage times: [3] transpose, [4] BC-back alone, [5] transpose + SBR-back + copy
+            // stage times: [3] transpose (+ group T factors), [4] BC-back alone,
+            // [5] transpose + SBR-back + copy
             EVD_CHECK(transpose_run(s, n, w.Qd, n, w.Qs, n));
+            const bool blocked = w.Tg && ctx->bcback_valu == 0 && bcback_mfma_fits(n);
+            if (blocked) EVD_CHECK(bcback_mfma_prepare(ctx, n, b, w.V, w.TAU, w.Tg, true));
             mark(4);
-            if (w.Tg && ctx->bcback_valu == 0)
-                EVD_CHECK(bcback_mfma_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n, w.Tg, true));
+            if (blocked)
+                EVD_CHECK(bcback_mfma_apply(ctx, n, n, b, w.V, w.Qs, n, w.Tg, true));
             else
                 EVD_CHECK(bcback_run_rev(ctx, n, n, b, w.V, w.TAU, w.Qs, n));
             mark(5);

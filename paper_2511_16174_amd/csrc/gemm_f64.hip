@@ -268,9 +268,10 @@ GemmPlan plan_gemm(int64_t m, int64_t n, int64_t k, size_t ws_elems)
     }
     p.splits = 1;
     p.kchunk = k;
-    // split K when the output grid cannot fill the chip and K is long
-    if (tiles < 256 && k >= 1024) {
-        int64_t want = evd_ceil_div(512, tiles);
+    // split K when the output grid gives fewer than about three workgroups
+    // per compute unit and K is long
+    if (tiles < 768 && k >= 1024) {
+        int64_t want = evd_ceil_div(768, tiles);
         int64_t maxs = k / 256;
         int64_t sp = want < maxs ? want : maxs;
         if (sp > 64) sp = 64;

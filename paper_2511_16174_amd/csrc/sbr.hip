@@ -152,8 +152,19 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
             while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
         __syncthreads();
         {
+            // records fetched eight at a time (all in flight), summed in
+            // the fixed order h = sub, sub + TPC, ...
             T s = 0.0;
-            for (int h = sub; h < G; h += TPC) s += ld_coh(&rec[(size_t)h * 2 * B + cq]);
+            for (int h0 = sub; h0 < G; h0 += 8 * TPC) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int h = h0 + u * TPC;
+                    v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + cq]) : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
+            }
             scr[tid] = s;
             if (tid < B) topsh[tid] = ld_coh(&rec[B + tid]);
             __syncthreads();

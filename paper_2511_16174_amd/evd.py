@@ -61,7 +61,8 @@ PROTOTYPES = {
     "evd_dstedc": (_st, [_vp, _c, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "evd_dorgsb_work_size": (_st, [_vp, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dorgsb": (_st, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _sz]),
-    "evd_dbcback": (_st, [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _i64]),
+    "evd_dbcback_work_size": (_st, [_vp, _i64, _i64, _vp]),
+    "evd_dbcback": (_st, [_vp, _c, _i64, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _sz]),
 }
 
 _lib = None
@@ -280,9 +281,15 @@ class Context:
         st = self.lib.evd_dorgsb(self.handle, n, b, _ptr(A), lda, _ptr(T), _ptr(Q), ldq, _ptr(work), work_bytes)
         self._check("evd_dorgsb", st)
 
-    def evd_dbcback(self, m_rows, n, b, V, TAU, Q, ldq):
+    def evd_dbcback_work_size(self, n, b) -> int:
+        s = _sz()
+        self._check("evd_dbcback_work_size", self.lib.evd_dbcback_work_size(self.handle, n, b, ctypes.byref(s)))
+        return s.value
+
+    def evd_dbcback(self, trans, m_rows, n, b, V, TAU, Q, ldq, work, work_bytes):
         self.set_stream()
-        st = self.lib.evd_dbcback(self.handle, m_rows, n, b, _ptr(V), _ptr(TAU), _ptr(Q), ldq)
+        st = self.lib.evd_dbcback(self.handle, trans.encode(), m_rows, n, b, _ptr(V), _ptr(TAU), _ptr(Q), ldq,
+                                  _ptr(work), work_bytes)
         self._check("evd_dbcback", st)
 
 

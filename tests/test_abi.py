@@ -60,6 +60,36 @@ def test_params(vctx):
     assert lib.evd_last_invalid_arg(h) == 2
     assert lib.evd_set_param(h, b"b", -1) == evd.EVD_ERR_INVALID_ARG
     assert lib.evd_last_invalid_arg(h) == 3
+    for key, good, bad in ((b"bcback_group", (0, 32, 64), (16, 48)), (b"bcback_rows", (0, 64, 128), (32, 96))):
+        for v in good:
+            assert lib.evd_set_param(h, key, v) == evd.EVD_OK
+        for v in bad:
+            assert lib.evd_set_param(h, key, v) == evd.EVD_ERR_INVALID_ARG
+            assert lib.evd_last_invalid_arg(h) == 3
+        assert lib.evd_set_param(h, key, 0) == evd.EVD_OK
+
+
+def test_bcback_work_size_and_argument_checks(vctx):
+    """The blocked BC-back needs T-factor scratch only for b = 16, 32, 64;
+    a short workspace is reported as such, before any device work."""
+    lib, h = vctx
+    sz = ctypes.c_size_t()
+    for b, blocked in ((4, False), (8, False), (16, True), (32, True), (64, True)):
+        assert lib.evd_dbcback_work_size(h, 300, b, ctypes.byref(sz)) == evd.EVD_OK
+        assert (sz.value > 0) == blocked
+    assert lib.evd_dbcback_work_size(h, 300, 48, ctypes.byref(sz)) == evd.EVD_ERR_INVALID_ARG
+    lib.evd_dbcback_work_size(h, 300, 64, ctypes.byref(sz))
+    need = sz.value
+    p = ctypes.c_void_p(256)  # never dereferenced: the checks fail first, or the context has no device
+    assert lib.evd_dbcback(h, b"X", 10, 300, 64, p, p, p, 10, p, need) == evd.EVD_ERR_INVALID_ARG
+    assert lib.evd_last_invalid_arg(h) == 2
+    assert lib.evd_dbcback(h, b"T", 10, 300, 64, p, p, p, 9, p, need) == evd.EVD_ERR_INVALID_ARG
+    assert lib.evd_last_invalid_arg(h) == 9
+    assert lib.evd_dbcback(h, b"N", 10, 300, 64, p, p, p, 10, None, need) == evd.EVD_ERR_INVALID_ARG
+    assert lib.evd_last_invalid_arg(h) == 10
+    assert lib.evd_dbcback(h, b"N", 10, 300, 64, p, p, p, 10, p, need - 8) == evd.EVD_ERR_WORKSPACE
+    assert lib.evd_last_invalid_arg(h) == 11
+    assert lib.evd_dbcback(h, b"N", 10, 300, 64, p, p, p, 10, p, need) == evd.EVD_ERR_HIP  # validation-only context
 
 
 @pytest.mark.parametrize("args,bad", [

@@ -32,9 +32,12 @@ def test_orgsb_matches_panel_product(n, b):
     assert M.orthogonality(Q) <= 10
 
 
+@pytest.mark.parametrize("trans", ["N", "T"])
 @pytest.mark.parametrize("n,b,mrows", [(40, 2, 40), (100, 4, 77), (300, 16, 300), (333, 32, 129),
-                                       (500, 64, 500), (130, 64, 1)])
-def test_bcback_matches_generation_order(n, b, mrows):
+                                       (500, 64, 500), (130, 64, 1), (701, 64, 203), (97, 16, 64)])
+def test_bcback_matches_generation_order(n, b, mrows, trans):
+    """Blocked matrix-core path (b = 16, 32, 64) and reflector-by-reflector
+    kernel (other b) against X Q_d / X Q_d^T formed from the reflectors."""
     from paper_2511_16174_amd import evd
     import torch
     ctx = evd.context(0)
@@ -42,11 +45,72 @@ def test_bcback_matches_generation_order(n, b, mrows):
     d, e, V, TAU, steps = run_bc(B, b)
     Qb = q_from_reflectors(n, b, V, TAU, steps)
     X = W.rng(5).standard_normal((mrows, n))
-    ref = X @ Qb
+    ref = X @ (Qb if trans == "N" else Qb.T)
     dX = to_dev(X)
     dV = to_dev(V.reshape(-1))
     dT = to_dev(TAU.reshape(-1))
-    ctx.evd_dbcback(mrows, n, b, dV, dT, dX, mrows)
+    wb = ctx.evd_dbcback_work_size(n, b)
+    assert (wb > 0) == (b in (16, 32, 64))
+    work = work_dev(wb)
+    ctx.evd_dbcback(trans, mrows, n, b, dV, dT, dX, mrows, work, wb)
     torch.cuda.synchronize()
+    out = from_dev(dX, mrows, n)
+    assert np.max(np.abs(out - ref)) <= 100 * n * M.EPS * np.abs(X).max()
+
+
+@pytest.mark.parametrize("n,b,mrows", [(333, 32, 129), (500, 64, 300)])
+def test_bcback_blocked_matches_valu_kernel(n, b, mrows):
+    """The blocked path and the reflector-by-reflector kernel give the same
+    product to rounding; a padded leading dimension is honoured."""
+    from paper_2511_16174_amd import evd
+    import torch
+    ctx = evd.context(0)
+    B = random_band(n, b, seed=7 * n + b)
+    d, e, V, TAU, steps = run_bc(B, b)
+    X = W.rng(9).standard_normal((mrows + 5, n))
+    dV = to_dev(V.reshape(-1))
+    dT = to_dev(TAU.reshape(-1))
+    wb = ctx.evd_dbcback_work_size(n, b)
+    outs = []
+    for valu in (0, 1):
+        ctx.set_param("bcback_valu", valu)
+        try:
+            dX = to_dev(X)
+            ctx.evd_dbcback("T", mrows, n, b, dV, dT, dX, mrows + 5, work_dev(wb), wb)
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_param("bcback_valu", 0)
+        outs.append(from_dev(dX, mrows + 5, n))
+    assert np.array_equal(outs[0][mrows:], X[mrows:])  # rows past m_rows untouched
+    assert np.max(np.abs(outs[0] - outs[1])) <= 50 * n * M.EPS * np.abs(X).max()
+
+
+@pytest.mark.parametrize("trans", ["N", "T"])
+@pytest.mark.parametrize("group,rows", [(32, 0), (64, 64), (64, 128)])
+def test_bcback_b64_group_and_row_variants(trans, group, rows):
+    """b = 64: 32- and 64-sweep groups, 64- and 128-row workgroups, on a size
+    with a ragged last group (n - 2 not a multiple of 64) and partial
+    workgroups (m_rows not a multiple of 128)."""
+    from paper_2511_16174_amd import evd
+    import torch
+    ctx = evd.context(0)
+    n, b, mrows = 389, 64, 300
+    B = random_band(n, b, seed=11)
+    d, e, V, TAU, steps = run_bc(B, b)
+    Qb = q_from_reflectors(n, b, V, TAU, steps)
+    X = W.rng(13).standard_normal((mrows, n))
+    ref = X @ (Qb if trans == "N" else Qb.T)
+    dX = to_dev(X)
+    dV = to_dev(V.reshape(-1))
+    dT = to_dev(TAU.reshape(-1))
+    wb = ctx.evd_dbcback_work_size(n, b)
+    ctx.set_param("bcback_group", group)
+    ctx.set_param("bcback_rows", rows)
+    try:
+        ctx.evd_dbcback(trans, mrows, n, b, dV, dT, dX, mrows, work_dev(wb), wb)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_param("bcback_group", 0)
+        ctx.set_param("bcback_rows", 0)
     out = from_dev(dX, mrows, n)
     assert np.max(np.abs(out - ref)) <= 100 * n * M.EPS * np.abs(X).max()
