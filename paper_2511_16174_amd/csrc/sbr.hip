@@ -346,12 +346,15 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     t.part = take((size_t)2 * PANEL_MAX_WGS * 2 * b + 64);
     t.Sg = take((size_t)b * b);
     t.taus = take((size_t)b);
-    // split-K workspace for the b x b product W^T X and the 2nb x b product
-    size_t ws = gemm_ws_elems_t<T>(b, b, n);
-    const size_t ws2 = gemm_ws_elems_t<T>(n, b, n);
-    const size_t ws3 = gemm_ws_elems_t<T>(2 * nb, b, n);
-    if (ws2 > ws) ws = ws2;
-    if (ws3 > ws) ws = ws3;
+    // split-K workspace for the products with K = the trailing size m of each
+    // panel (A_2 W, W^T X, [Z_J Y_J]^T W); the split count grows as m falls,
+    // so take the largest need over every panel's m
+    size_t ws = 0;
+    for (int64_t m = n - b; m > 0; m -= b) {
+        const size_t c[3] = {gemm_ws_elems_t<T>(m, b, m), gemm_ws_elems_t<T>(b, b, m),
+                             gemm_ws_elems_t<T>(2 * nb, b, m)};
+        for (size_t v : c) ws = v > ws ? v : ws;
+    }
     t.gemm_ws = take(ws);
     t.gemm_ws_elems = ws;
     t.bar = (int *)take((PANEL_MAX_WGS + 64) * sizeof(int) / sizeof(T));
