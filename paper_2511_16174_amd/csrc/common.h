@@ -255,8 +255,13 @@ evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t 
 
 // One K-slice of a GEMM operand tile is an LC x LS block in memory (LC
 // contiguous elements, lines ld apart).  Thread tid loads elements
-// e = tid + r*NT, (c, s) = (e % LC, e / LC), through a uniform base pointer and
-// 32-bit offsets; interior slices skip the bounds tests.
+// e = tid + r*NT, (c, s) = (e % LC, e / LC) with buffer loads through a
+// descriptor based at the (wave-uniform) slice origin: elements outside
+// c < cmax, s < smax get an offset past the descriptor's range, which the
+// hardware turns into a zero, so edge slices need no branches around the
+// loads.  Requires ((LS - 1) ld + LC) sizeof(T) < 2^31 (checked by the host).
+constexpr uint32_t EVD_BUF_DWORD3 = 0x00020000u;  // raw buffer, 32-bit data format (gfx9 family)
+constexpr uint32_t EVD_BUF_OOB = 0x80000000u;     // offset beyond any range the loaders use
 template <typename T, int LC, int LS, int NT>
 struct TileSlice {
     static constexpr int E = LC * LS / NT;
@@ -267,18 +272,24 @@ struct TileSlice {
     static __device__ __forceinline__ void load(T (&v)[E], const T *__restrict__ base, int ld, int tid,
                                                 bool full, int64_t cmax, int64_t smax)
     {
-        if (full) {
+        const uint32_t nrec = ((uint32_t)(LS - 1) * (uint32_t)ld + LC) * (uint32_t)sizeof(T);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)nrec,
+                                                                           (int)EVD_BUF_DWORD3);
+        const int cm = (int)(cmax < LC ? cmax : LC), sm = (int)(smax < LS ? smax : LS);
 #pragma unroll
-            for (int r = 0; r < E; ++r) v[r] = base[c(tid, r) + s(tid, r) * ld];
-        } else {
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const int cc = c(tid, r), ss = s(tid, r);
-                v[r] = (cc < cmax && ss < smax) ? base[cc + ss * ld] : (T)0;
-            }
+        for (int r = 0; r < E; ++r) {
+            const int cc = c(tid, r), ss = s(tid, r);
+            uint32_t off = (uint32_t)(cc + ss * ld) * (uint32_t)sizeof(T);
+            if (!full) off = (cc < cm && ss < sm) ? off : EVD_BUF_OOB;
+            if constexpr (sizeof(T) == 8)
+                v[r] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+            else
+                v[r] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
         }
     }
 };
+// leading dimensions the slice loaders accept (byte offsets stay below 2^31)
+inline bool evd_gemm_ld_ok(int64_t ld) { return ld > 0 && ld <= ((int64_t)1 << 21); }
 
 // Type-dispatched GEMM: FP64 MFMA for double, split-BF16x3 for float.
 inline evd_status_t gemm_t(hipStream_t s, int opa, int opb, int lower_c, int64_t m, int64_t n, int64_t k, double alpha,

@@ -269,6 +269,7 @@ evd_status_t gemm_f32x3(hipStream_t s, int opa, int opb, int lower_c, int64_t m,
                            (int64_t)0, 0.0f, beta, C, ldc, lower_c);
         return evd_check_last();
     }
+    if (!evd_gemm_ld_ok(lda) || !evd_gemm_ld_ok(ldb)) return EVD_ERR_INVALID_ARG;  // slice loader offsets
     Plan3 p = plan3(m, n, k, ws ? ws_elems : 0);
     const int lower = lower_c ? 1 : 0;
     dim3 grid((unsigned)evd_ceil_div(m, p.bm), (unsigned)evd_ceil_div(n, p.bn), (unsigned)p.splits);

@@ -7,10 +7,13 @@
 //
 // Design: a workgroup computes a BM x BN tile of C with (BM/WM) x (BN/WN)
 // wavefronts; each wavefront owns a WM x WN sub-tile made of 16 x 16
-// accumulators of v_mfma_f64_16x16x4 (1024 FMAs per instruction).  K is
-// staged through LDS in slices of 16 with two buffers (one barrier per
-// slice; the global loads of slice t+1 are in flight while slice t is
-// multiplied).  The MFMA is issued with the B fragment as its first operand,
+// accumulators of v_mfma_f64_16x16x4 (1024 FMAs per instruction).  The large
+// tiles use eight wavefronts of 64 x 32 or 32 x 32 (about 120 VGPRs, so two
+// workgroups and four wavefronts per SIMD share a CU).  K is staged through
+// LDS in slices of 16 with two buffers (one barrier per slice; the global
+// loads of slice t+1 are in flight while slice t is multiplied).  Slices are
+// fetched with buffer loads whose out-of-range lanes read zero, so edge tiles
+// run the same branch-free loop as interior ones.  The MFMA is issued with the B fragment as its first operand,
 // so each group of 16 lanes holds 16 consecutive rows of one column of C and
 // the stores are coalesced along the column-major C.  (Accumulator layout of
 // v_mfma_f64_16x16x4: lane l, element r holds D(l/16 + 4 r, l % 16).)
@@ -24,6 +27,14 @@ namespace {
 
 constexpr int BK = 16;
 constexpr int PAD = 1;
+
+// waves per SIMD to budget registers for: 8-wavefront tiles (two workgroups
+// per CU, four waves per SIMD) fit 128 VGPRs, 4-wavefront tiles 256; the
+// symmetric-operand loader needs more
+constexpr int gemm_min_waves(int BM, int BN, int WM, int WN, int OPA)
+{
+    return ((BM / WM) * (BN / WN) >= 8 ? 4 : 2) / (OPA == OP_S ? 2 : 1);
+}
 
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
 __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64_t kbeg, int64_t kend, int64_t m0,
@@ -174,7 +185,7 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
 }
 
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, (OPA == OP_S) ? 1 : 2) void gemm_f64_kernel(
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, WM, WN, OPA)) void gemm_f64_kernel(
     int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
     int64_t split_stride)
@@ -190,7 +201,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, (OPA == OP_S) ? 1 : 2) 
 // Grouped product with sizes in device memory: problem blockIdx.z, C = A B
 // (op N, N); tiles outside the problem exit.
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 2) void gemm_f64_grouped_kernel(const GemmProblem *probs)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, WM, WN, OP_N)) void gemm_f64_grouped_kernel(const GemmProblem *probs)
 {
     const GemmProblem p = probs[blockIdx.z];
     const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
@@ -291,7 +302,7 @@ evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob
     if (nprob > 65535) return EVD_ERR_INVALID_ARG;
     if (max_m > 64 && max_n > 64 && max_m * max_n >= (int64_t)512 * 128 * 128) {
         dim3 grid((unsigned)evd_ceil_div(max_m, 128), (unsigned)evd_ceil_div(max_n, 128), (unsigned)nprob);
-        hipLaunchKernelGGL((gemm_f64_grouped_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, probs);
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<128, 128, 64, 32>), grid, dim3(512), 0, s, probs);
     } else {
         dim3 grid((unsigned)evd_ceil_div(max_m, 64), (unsigned)evd_ceil_div(max_n, 64), (unsigned)nprob);
         hipLaunchKernelGGL((gemm_f64_grouped_kernel<64, 64, 32, 32>), grid, dim3(256), 0, s, probs);
@@ -319,6 +330,7 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
                            lower_c);
         return evd_check_last();
     }
+    if (!evd_gemm_ld_ok(lda) || !evd_gemm_ld_ok(ldb)) return EVD_ERR_INVALID_ARG;  // slice loader offsets
     GemmPlan p = plan_gemm(m, n, k, ws ? ws_elems : 0);
     const int lower = lower_c ? 1 : 0;
     dim3 grid((unsigned)evd_ceil_div(m, p.bm), (unsigned)evd_ceil_div(n, p.bn), (unsigned)p.splits);
@@ -333,13 +345,13 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         bta = 0.0;
     }
     if (p.bm == 128 && p.bn == 128)
-        launch_ops<128, 128, 64, 64>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
+        launch_ops<128, 128, 64, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
                                      sstride);
     else if (p.bm == 128 && p.bn == 64)
-        launch_ops<128, 64, 64, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
+        launch_ops<128, 64, 32, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
                                     sstride);
     else if (p.bm == 64 && p.bn == 128)
-        launch_ops<64, 128, 32, 64>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
+        launch_ops<64, 128, 32, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
                                     sstride);
     else
         launch_ops<64, 64, 32, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
