@@ -34,7 +34,7 @@
 
 namespace {
 
-constexpr int PANEL_THREADS = 256;
+constexpr int PANEL_THREADS = 1024;
 constexpr int PANEL_MAX_WGS = 256;  // workgroups of one panel launch (at most)
 constexpr int PANEL_WGS = 128;      // workgroups of one panel launch (target)
 
@@ -88,6 +88,35 @@ __global__ void extract_diag_blocks_kernel(int64_t n, int64_t b, int64_t tail0, 
     for (int64_t d = threadIdx.x; j + d < limit; d += blockDim.x) AB[d + j * ldab] = A[j + d + j * lda];
 }
 
+// Thread layout of the panel kernel's column phases: column cq gets TPC =
+// PANEL_THREADS / B threads; the first L = min(TPC, 64) of them are adjacent
+// lanes of one wavefront (their partial sums meet through lane shuffles),
+// and for narrow panels (TPC > 64) WPC = TPC / 64 wavefronts share a column.
+template <int B>
+struct PanelLayout {
+    static constexpr int TPC = PANEL_THREADS / B;
+    static constexpr int L = TPC < 64 ? TPC : 64;
+    static constexpr int WPC = TPC / L;
+    static __device__ __forceinline__ int col(int tid)
+    {
+        return (WPC == 1) ? (tid >> 6) * (64 / L) + (tid & 63) / L : (tid >> 6) / WPC;
+    }
+    static __device__ __forceinline__ int sub(int tid)
+    {
+        return (WPC == 1) ? (tid & 63) % L : (tid & 63) + 64 * ((tid >> 6) % WPC);
+    }
+};
+
+// sum over the L adjacent lanes of a column (xor butterfly: every lane ends
+// with the same bits, the additions being commutative pairwise)
+template <int L, typename T>
+__device__ __forceinline__ T lane_group_sum(T v)
+{
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 template <int B, typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, T *P, int64_t lda,
                                                                  T *Y1, T *Y2, int64_t ldy, T *part,
@@ -95,26 +124,34 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
                                                                  T *AB, int64_t ldab, int64_t j0, int *flags,
                                                                  int epoch0)
 {
-    // part[(j & 1) * PANEL_MAX_WGS * 2B + h * 2B + q]: record of workgroup h for
-    // column j (double-buffered by column parity): [0, B) its partial sums,
-    // [B, 2B) row j of the panel (workgroup 0 only).  flags[h]: epoch of the
-    // last column workgroup h has published.  Every workgroup reads all
-    // records and sums them in the same order, so all hold identical sums.
+    // Workgroup g holds rows r0 .. r0 + chunk - 1 of the m x B panel in LDS.
+    // Per column j: (1) every workgroup forms its partial sums
+    // h_q = sum_{rows i > j} P(i, j) P(i, q) for all q; (2) the partial sums of
+    // all workgroups are combined (through records in device memory when
+    // G > 1: part[(j & 1) * PANEL_MAX_WGS * 2B + h * 2B + q] holds workgroup
+    // h's sums in [0, B) and, for h = 0, row j of the panel in [B, 2B);
+    // flags[h] is the epoch of the last column h published; every workgroup
+    // sums all records in the same order, so all hold identical sums);
+    // (3) every thread forms the Householder scalars of column j and the
+    // workgroup applies H_j to its rows of columns j+1 .. B-1.  Columns are
+    // kept unscaled (v_j = scale_j * P(:, j) below row j) until the write-back.
+    using LY = PanelLayout<B>;
+    constexpr int TPC = LY::TPC, L = LY::L, WPC = LY::WPC;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T *smem = (T *)smem_raw;
-    const int ldp = chunk + 1;
+    const int ldp = chunk + 16;   // columns 32 banks apart: the two half-waves of a read do not collide
     T *Ps = smem;                 // Ps[q * ldp + i]: panel column q, local row i
+    T *scr = Ps + B * ldp;        // WPC * B partial sums (narrow panels)
     __shared__ T hsh[B];
     __shared__ T topsh[B];
-    __shared__ T coef[B];
+    __shared__ T scales[B];
     __shared__ T betas[B];
-    __shared__ T scal[4];
 
-    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int64_t r0 = (int64_t)g * chunk;
     const int rows = (int)((m - r0) < chunk ? (m - r0) : chunk);
     const int nr = (int)(m < B ? m : B);
-    T *scr = Ps + B * ldp;        // PANEL_THREADS doubles of scratch after the panel
+    const int cq = LY::col(tid), sub = LY::sub(tid);
 
     for (int e = tid; e < rows * B; e += PANEL_THREADS) {
         const int i = e % rows, q = e / rows;
@@ -122,103 +159,93 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     }
     __syncthreads();
 
-    constexpr int TPC = PANEL_THREADS / B;  // threads per column in the dot phases
-    const int cq = tid % B, sub = tid / B;
     for (int j = 0; j < nr; ++j) {
         const int E = epoch0 + j + 1;
         T *rec = part + (size_t)(j & 1) * PANEL_MAX_WGS * 2 * B;
-        // ---- partial sums h_q = sum over local rows i > j of P(i, j) P(i, q), all q:
-        // q = j is the squared norm below the diagonal, q > j gives v_j^T P(:, q)
-        // and q < j gives Y(:, q)^T v_j (both up to the row-j term and the scale)
+        // ---- (1) partial sums of column cq against column j over local rows below j
+        T acc = 0.0;
         {
-            T acc = 0.0;
-            for (int i = sub; i < rows; i += TPC)
-                if (r0 + i > j) acc += Ps[j * ldp + i] * Ps[cq * ldp + i];
-            scr[tid] = acc;
-            __syncthreads();
-            if (tid < B) {
-                T s = 0.0;
-#pragma unroll
-                for (int t = 0; t < TPC; ++t) s += scr[tid + t * B];
-                st_coh(&rec[(size_t)g * 2 * B + tid], s);
-                if (g == 0) st_coh(&rec[B + tid], Ps[tid * ldp + j]);  // row j lives in chunk 0
-            }
+            const int i0 = (int)((j + 1 - r0) > 0 ? (j + 1 - r0) : 0);  // first local row below j
+            const T *pj = Ps + j * ldp, *pq = Ps + cq * ldp;
+#pragma unroll 4
+            for (int i = i0 + sub; i < rows; i += TPC) acc += pj[i] * pq[i];
         }
-        mem_drain();
-        __syncthreads();
-        if (tid == 0) st_coh(&flags[g], E);
-        // ---- wait for every record of this column, then reduce them all
-        if (tid < G)
-            while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
-        __syncthreads();
-        {
-            // records fetched eight at a time (all in flight), summed in
-            // the fixed order h = sub, sub + TPC, ...
-            T s = 0.0;
-            for (int h0 = sub; h0 < G; h0 += 8 * TPC) {
-                T v[8];
+        acc = lane_group_sum<L>(acc);
+        if (WPC > 1) {
+            if (lane == 0) scr[cq * WPC + (tid >> 6) % WPC] = acc;
+            __syncthreads();
+            acc = 0.0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int h = h0 + u * TPC;
-                    v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + cq]) : (T)0;
-                }
+            for (int w = 0; w < WPC; ++w) acc += scr[cq * WPC + w];
+        }
+        if (G == 1) {
+            // one workgroup holds the whole column
+            if (sub == 0) hsh[cq] = acc;
+            if (tid < B) topsh[tid] = Ps[tid * ldp + j];
+        } else {
+            if (sub == 0) st_coh(&rec[(size_t)g * 2 * B + cq], acc);
+            if (g == 0 && tid < B) st_coh(&rec[B + tid], Ps[tid * ldp + j]);  // row j lives in chunk 0
+            mem_drain();
+            __syncthreads();
+            if (tid == 0) st_coh(&flags[g], E);
+            // ---- (2) wait for every record of this column, then sum them:
+            // a thread's records h = sub, sub + TPC, ... are all requested
+            // before the first is used, summed in that order, then across the
+            // column's threads as in (1)
+            if (tid < G)
+                while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
+            __syncthreads();
+            constexpr int MAXR = (PANEL_MAX_WGS + TPC - 1) / TPC;
+            T v[MAXR];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) s += v[u];
+            for (int u = 0; u < MAXR; ++u) {
+                const int h = sub + u * TPC;
+                v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + cq]) : (T)0;
             }
-            scr[tid] = s;
+            T s2 = 0.0;
+#pragma unroll
+            for (int u = 0; u < MAXR; ++u) s2 += v[u];
+            s2 = lane_group_sum<L>(s2);
+            if (WPC > 1) {
+                __syncthreads();
+                if (lane == 0) scr[cq * WPC + (tid >> 6) % WPC] = s2;
+                __syncthreads();
+                s2 = 0.0;
+#pragma unroll
+                for (int w = 0; w < WPC; ++w) s2 += scr[cq * WPC + w];
+            }
+            if (sub == 0) hsh[cq] = s2;
             if (tid < B) topsh[tid] = ld_coh(&rec[B + tid]);
-            __syncthreads();
-            if (tid < B) {
-                T r = 0.0;
-#pragma unroll
-                for (int t = 0; t < TPC; ++t) r += scr[tid + t * B];
-                hsh[tid] = r;
-            }
         }
         __syncthreads();
-        // ---- Householder vector of column j: v = (x - beta e_j) / (x_j - beta)
+        // ---- (3) Householder vector of column j: v = (x - beta e_j) / (x_j - beta)
+        const T x0 = topsh[j], sig = hsh[j];
+        T tau = 0.0, beta = x0, scale = 0.0;
+        if (sig != 0.0) {
+            const T nrm = sqrt(x0 * x0 + sig);
+            beta = (x0 >= 0.0) ? -nrm : nrm;
+            tau = (beta - x0) / beta;
+            scale = 1.0 / (x0 - beta);
+        }
         if (tid == 0) {
-            const T x0 = topsh[j], sig = hsh[j];
-            T tau = 0.0, beta = x0, scale = 0.0;
-            if (sig != 0.0) {
-                const T nrm = sqrt(x0 * x0 + sig);
-                beta = (x0 >= 0.0) ? -nrm : nrm;
-                tau = (beta - x0) / beta;
-                scale = 1.0 / (x0 - beta);
-            }
-            scal[0] = tau;
-            scal[1] = beta;
-            scal[2] = scale;
+            scales[j] = scale;
+            betas[j] = beta;
+            if (g == 0) taus[j] = tau;
         }
-        __syncthreads();
-        const T tau = scal[0], scale = scal[2];
-        if (tid < B) {
-            const T d = topsh[tid] + scale * hsh[tid];
-            coef[tid] = tau * d;
-            if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = d;  // (Y[:, 0:j]^T v_j)
-        }
-        if (g == 0 && tid == 0) {
-            taus[j] = tau;
-            betas[j] = scal[1];
-        }
-        __syncthreads();
-        // ---- apply H_j to the remaining columns of the chunk, then store v_j
+        // Y(:, q)^T v_j for q < j, with column q's own scale applied
+        if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = scales[tid] * (topsh[tid] + scale * hsh[tid]);
         if (tau != 0.0) {
+            // rows i >= j of columns q > j: P(i, q) -= v_i tau (v_j^T P(:, q))
             const int ncols = B - j - 1;
-            for (int e = tid; e < rows * ncols; e += PANEL_THREADS) {
-                const int i = e % rows, q = j + 1 + e / rows;
-                const int64_t gi = r0 + i;
-                if (gi >= j) {
-                    const T v = (gi == j) ? (T)1 : scale * Ps[j * ldp + i];
-                    Ps[q * ldp + i] -= v * coef[q];
-                }
+            const int i0 = (int)((j - r0) > 0 ? (j - r0) : 0);
+            const int nrow = rows - i0;
+            const T *pj = Ps + j * ldp;
+            for (int e = tid; e < nrow * ncols; e += PANEL_THREADS) {
+                const int i = i0 + e % nrow, q = j + 1 + e / nrow;
+                const T vi = (r0 + i == j) ? (T)1 : scale * pj[i];
+                const T cf = tau * (topsh[q] + scale * hsh[q]);
+                Ps[q * ldp + i] -= vi * cf;
             }
-        }
-        __syncthreads();
-        for (int i = tid; i < rows; i += PANEL_THREADS) {
-            const int64_t gi = r0 + i;
-            if (gi > j) Ps[j * ldp + i] *= scale;
-            else if (gi == j) Ps[j * ldp + i] = 1.0;
         }
         __syncthreads();
     }
@@ -229,7 +256,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
         const int i = e % rows, q = e / rows;
         const int64_t gi = r0 + i;
         T y = 0.0;
-        if (q < nr) y = (gi > q) ? Ps[q * ldp + i] : (gi == q ? 1.0 : 0.0);
+        if (q < nr) y = (gi > q) ? scales[q] * Ps[q * ldp + i] : (gi == q ? 1.0 : 0.0);
         P[gi + (int64_t)q * lda] = y;
         Y1[gi + (int64_t)q * ldy] = y;
         Y2[gi + (int64_t)q * ldy] = y;
@@ -270,15 +297,15 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T 
     int maxg = PANEL_WGS;
     if (ctx->panel_wgs > 0 && ctx->panel_wgs < maxg) maxg = (int)ctx->panel_wgs;
     int64_t chunk = evd_ceil_div(m, maxg);
-    const int64_t lds_rows = (140 * 1024 / (int64_t)sizeof(T) - 2 * PANEL_THREADS) / B;
+    const int64_t lds_rows = (140 * 1024 / (int64_t)sizeof(T) - PANEL_THREADS) / B - 16;
     if (chunk > lds_rows) chunk = lds_rows;
     if (chunk < B) chunk = B;
-    chunk = evd_ceil_div(chunk, 16) * 16;
-    if (evd_ceil_div(m, chunk) > PANEL_MAX_WGS) chunk = evd_ceil_div(evd_ceil_div(m, PANEL_MAX_WGS), 16) * 16;
+    chunk = evd_ceil_div(chunk, 32) * 32;
+    if (evd_ceil_div(m, chunk) > PANEL_MAX_WGS) chunk = evd_ceil_div(evd_ceil_div(m, PANEL_MAX_WGS), 32) * 32;
     int G = (int)evd_ceil_div(m, chunk);
-    // LDS: B columns plus one scratch column of PANEL_THREADS doubles
-    int64_t ldp = chunk + 1;
-    size_t lds = (size_t)(B * ldp + (ldp > PANEL_THREADS ? ldp : PANEL_THREADS)) * sizeof(T);
+    // LDS: B columns of chunk + 16 rows plus the narrow-panel partial sums
+    const int64_t ldp = chunk + 16;
+    size_t lds = (size_t)(B * ldp + PANEL_THREADS) * sizeof(T);
     if (lds < (size_t)B * B * sizeof(T)) lds = (size_t)B * B * sizeof(T);
     if (lds > 150 * 1024) return EVD_ERR_INVALID_ARG;
     int chunk_i = (int)chunk;
