@@ -338,6 +338,7 @@ __global__ __launch_bounds__(256, 2) void bcback_mfma_kernel(int64_t mrows, int6
 // masking), and -T (or -T^T for the reverse order) as its nonzero 16 x 4
 // tiles, each stored in the lane order of the matrix-core operand.
 constexpr int BC_GW = 64;
+constexpr int B_MAX_WIDE = 64;  // band widths the wide-group T kernel accepts
 
 template <int G>
 __host__ __device__ constexpr int wide_tiles() { return (G / 16) * (G / 4) - 2 * (G / 16) * (G / 16 - 1); }
@@ -358,10 +359,11 @@ __global__ __launch_bounds__(256) void bct_wide_kernel(int64_t n, int B, const d
                                                        int64_t nblk)
 {
     constexpr int NTT = wide_tiles<G>();
-    __shared__ double vsh[G][65];
+    static_assert(B_MAX_WIDE + 1 >= G + 1, "T shares the vectors' LDS");
+    __shared__ double vsh[G][B_MAX_WIDE + 1];  // the vectors, then (after the Gram matrix) T
     __shared__ double gsh[G][G + 1];
-    __shared__ double tsh[G][G + 1];
     __shared__ double tau[G];
+    double (*tsh)[B_MAX_WIDE + 1] = vsh;
     const int64_t blk = blockIdx.x, s = blockIdx.y;
     const int64_t nsweeps = n - 2, nsteps = bc_num_steps(n, B);
     const int tid = threadIdx.x;
@@ -379,7 +381,6 @@ __global__ __launch_bounds__(256) void bct_wide_kernel(int64_t n, int B, const d
         const int64_t c = blk * G + j;
         tau[j] = (c < nsweeps && s < nsteps) ? TAU[s * n + c] : 0.0;
     }
-    for (int e = tid; e < G * (G + 1); e += 256) (&tsh[0][0])[e] = 0.0;
     __syncthreads();
     for (int e = tid; e < G * G; e += 256) {
         const int i = e / G, j = e % G;
@@ -391,12 +392,17 @@ __global__ __launch_bounds__(256) void bct_wide_kernel(int64_t n, int B, const d
         }
     }
     __syncthreads();
+    for (int e = tid; e < G * (B_MAX_WIDE + 1); e += 256) (&tsh[0][0])[e] = 0.0;
+    __syncthreads();
+    // column j: row p of -tau_j T[0:j, 0:j] g[0:j, j] split over 4 adjacent threads
     for (int j = 0; j < G; ++j) {
-        if (tid < j) {
-            double acc = 0.0;
-            for (int k = tid; k < j; ++k) acc += tsh[tid][k] * gsh[k][j];
-            tsh[tid][j] = -tau[j] * acc;
-        }
+        const int p = tid >> 2, u = tid & 3;
+        double acc = 0.0;
+        if (p < j)
+            for (int k = p + u; k < j; k += 4) acc += tsh[p][k] * gsh[k][j];
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (p < j && u == 0) tsh[p][j] = -tau[j] * acc;
         if (tid == 0) tsh[j][j] = tau[j];
         __syncthreads();
     }

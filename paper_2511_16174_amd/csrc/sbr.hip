@@ -275,9 +275,18 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     T *Ts = smem;
     for (int e = tid; e < B * B; e += PANEL_THREADS) Ts[e] = 0.0;
     __syncthreads();
+    // column j: T[0:j, j] = -tau_j T[0:j, 0:j] Sg[0:j, j]; row p of the
+    // product is split over the TPC adjacent threads of row p (TPC <= 64)
     for (int j = 0; j < B; ++j) {
         const T tj = (j < nr) ? taus[j] : 0.0;
-        if (tid < j) {
+        if (TPC <= 64) {
+            const int p = tid / TPC, u = tid % TPC;
+            T s = 0.0;
+            if (p < j)
+                for (int r = p + u; r < j; r += TPC) s += Ts[p + r * B] * Sg[r + (int64_t)j * B];
+            s = lane_group_sum<(TPC <= 64 ? TPC : 64)>(s);
+            if (p < j && u == 0) Ts[p + j * B] = -tj * s;
+        } else if (tid < j) {
             T s = 0.0;
             for (int r = tid; r < j; ++r) s += Ts[tid + r * B] * Sg[r + (int64_t)j * B];
             Ts[tid + j * B] = -tj * s;
