@@ -33,6 +33,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str, n: int, b: int):
+    """HBM bytes per launch of `kernel` at this workload, from the committed
+    rocprofv3 counter summary profiles/<kernel>_n<n>_b<b>_traffic.md
+    (FETCH_SIZE and WRITE_SIZE runs of this same bench command, each scaled by
+    what the counter reads for a plain device copy of known size).  None when
+    there is no summary or the kernel's source has changed since the counters
+    were taken (the summary records the source file's SHA-256)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_n{n}_b{b}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    try:
+        src = os.path.join(ROOT, fields["source"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != fields["source_sha256"]:
+                return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def cpu_baseline(n: int = 2048):
     """The CPU oracle (one-stage Householder + implicit QL, with vectors) on a
     bounded sample of the same workload: one n x n matrix of the same recipe."""
@@ -251,10 +278,13 @@ def main():
             bound = "mfma" if blocked else "alu"
         else:
             kdesc, bound = "gemm_f64_kernel (final Q_sb Q_d)", "mfma"
+        traffic = measured_traffic(kdesc, n, b) if kname == "bc_back" else None
         roofline = {"kernel": kdesc, "bound": bound,
                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                    "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                     "algorithmic_flops_per_launch": 2.0 * n ** 3, "launch_ms": round(kms, 3)}
+        if traffic:
+            roofline["traffic_GBps"] = round(traffic / (kms * 1e-3) / 1e9, 1)
     else:
         roofline = None
 

@@ -27,6 +27,7 @@ namespace {
 
 constexpr int BK = 16;
 constexpr int PAD = 1;
+int g_gemm_swizzle = 1;  // XCD-aware tile order (gemm_tile); not used for triangular outputs, where it was slower
 
 // waves per SIMD to budget registers for: 8-wavefront tiles (two workgroups
 // per CU, four waves per SIMD) fit 128 VGPRs, 4-wavefront tiles 256; the
@@ -184,13 +185,38 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
     }
 }
 
+// Output tile of this workgroup.  Workgroups are dispatched round-robin over
+// the eight XCDs (each with its own L2), so the linear id is first made
+// XCD-contiguous (the workgroups resident on one XCD get consecutive ids),
+// then ids walk groups of GM tile rows column by column, so the tiles that
+// share an XCD's L2 at a time reuse the same few A row strips and B column
+// strips.  Both steps are bijections on the grid.
+__device__ __forceinline__ void gemm_tile(int swz, int &bx, int &by)
+{
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    if (!swz) return;
+    constexpr int XCD = 8, GM = 8;
+    const int nbx = gridDim.x, nby = gridDim.y, total = nbx * nby;
+    int pid = bx + by * nbx;
+    const int full = (total / XCD) * XCD;
+    if (pid < full) pid = (pid % XCD) * (total / XCD) + pid / XCD;
+    const int group = pid / (GM * nby), first = group * GM;
+    const int gsz = (nbx - first) < GM ? (nbx - first) : GM;
+    const int r = pid - group * GM * nby;
+    bx = first + r % gsz;
+    by = r / gsz;
+}
+
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, WM, WN, OPA)) void gemm_f64_kernel(
     int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
-    int64_t split_stride)
+    int64_t split_stride, int swz)
 {
-    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    int bx, by;
+    gemm_tile(swz, bx, by);
+    const int64_t m0 = (int64_t)bx * BM, n0 = (int64_t)by * BN;
     if (LOWER && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
     const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
@@ -234,7 +260,7 @@ void launch_cfg(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64
 {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, OPA, OPB, LOWER>), grid, dim3(NT), 0, s, m, n, k, kchunk,
-                       alpha, A, lda, B, ldb, beta, C, ldc, split_stride);
+                       alpha, A, lda, B, ldb, beta, C, ldc, split_stride, LOWER ? 0 : g_gemm_swizzle);
 }
 
 template <int BM, int BN, int WM, int WN>
