@@ -195,27 +195,33 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
             if (tid < G)
                 while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
             __syncthreads();
-            constexpr int MAXR = (PANEL_MAX_WGS + TPC - 1) / TPC;
-            T v[MAXR];
-#pragma unroll
-            for (int u = 0; u < MAXR; ++u) {
-                const int h = sub + u * TPC;
-                v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + cq]) : (T)0;
-            }
+            // records are read whole: wavefront w takes records
+            // h = w, w + NWV, ..., lane q their entry q (contiguous 8B x B
+            // loads, all requested before the first is used); the NWV
+            // partial sums per entry are then added in wavefront order
+            constexpr int NWV = PANEL_THREADS / 64;
+            constexpr int MAXR = (PANEL_MAX_WGS + NWV - 1) / NWV;
+            const int w = tid >> 6;
             T s2 = 0.0;
+            if (lane < B) {
+                T v[MAXR];
 #pragma unroll
-            for (int u = 0; u < MAXR; ++u) s2 += v[u];
-            s2 = lane_group_sum<L>(s2);
-            if (WPC > 1) {
-                __syncthreads();
-                if (lane == 0) scr[cq * WPC + (tid >> 6) % WPC] = s2;
-                __syncthreads();
-                s2 = 0.0;
+                for (int u = 0; u < MAXR; ++u) {
+                    const int h = w + u * NWV;
+                    v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + lane]) : (T)0;
+                }
 #pragma unroll
-                for (int w = 0; w < WPC; ++w) s2 += scr[cq * WPC + w];
+                for (int u = 0; u < MAXR; ++u) s2 += v[u];
+                scr[w * B + lane] = s2;
             }
-            if (sub == 0) hsh[cq] = s2;
             if (tid < B) topsh[tid] = ld_coh(&rec[B + tid]);
+            __syncthreads();
+            if (tid < B) {
+                T r = 0.0;
+#pragma unroll
+                for (int u = 0; u < NWV; ++u) r += scr[u * B + tid];
+                hsh[tid] = r;
+            }
         }
         __syncthreads();
         // ---- (3) Householder vector of column j: v = (x - beta e_j) / (x_j - beta)
