@@ -34,9 +34,9 @@
 
 namespace {
 
-constexpr int PANEL_THREADS = 1024;
+constexpr int PANEL_THREADS = 512;
 constexpr int PANEL_MAX_WGS = 256;  // workgroups of one panel launch (at most)
-constexpr int PANEL_WGS = 128;      // workgroups of one panel launch (target)
+constexpr int PANEL_WGS = 64;       // workgroups of one panel launch (target)
 
 template <typename T>
 __global__ void fill_kernel(T *p, int64_t count, T v)
@@ -117,6 +117,15 @@ __device__ __forceinline__ T lane_group_sum(T v)
     return v;
 }
 
+// Rows of one workgroup's slice of the panel: R rows per thread, held in
+// registers (thread (sub, cq) holds rows sub, sub + TPC, ... of column cq).
+template <int B>
+struct PanelRows {
+    static constexpr int TPC = PanelLayout<B>::TPC;
+    static constexpr int CH = (64 * TPC < 2048) ? 64 * TPC : 2048;  // rows per workgroup at most
+    static constexpr int R = CH / TPC;
+};
+
 template <int B, typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, T *P, int64_t lda,
                                                                  T *Y1, T *Y2, int64_t ldy, T *part,
@@ -124,94 +133,107 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
                                                                  T *AB, int64_t ldab, int64_t j0, int *flags,
                                                                  int epoch0)
 {
-    // Workgroup g holds rows r0 .. r0 + chunk - 1 of the m x B panel in LDS.
-    // Per column j: (1) every workgroup forms its partial sums
-    // h_q = sum_{rows i > j} P(i, j) P(i, q) for all q; (2) the partial sums of
-    // all workgroups are combined (through records in device memory when
-    // G > 1: part[(j & 1) * PANEL_MAX_WGS * 2B + h * 2B + q] holds workgroup
-    // h's sums in [0, B) and, for h = 0, row j of the panel in [B, 2B);
-    // flags[h] is the epoch of the last column h published; every workgroup
-    // sums all records in the same order, so all hold identical sums);
-    // (3) every thread forms the Householder scalars of column j and the
-    // workgroup applies H_j to its rows of columns j+1 .. B-1.  Columns are
-    // kept unscaled (v_j = scale_j * P(:, j) below row j) until the write-back.
+    // Workgroup g holds rows r0 .. r0 + chunk - 1 of the m x B panel in
+    // registers.  Per column j: (1) the owners of column j put it in LDS;
+    // every thread forms its partial sums h_q = sum_{rows i > j} P(i, j) P(i, q)
+    // for its column q; (2) the partial sums of all workgroups are combined
+    // (through records in device memory when G > 1:
+    // part[(j & 1) * PANEL_MAX_WGS * 2B + h * 2B + q] holds workgroup h's sums
+    // in [0, B) and, for h = 0, row j of the panel in [B, 2B); flags[h] is the
+    // epoch of the last column h published; every workgroup sums all records
+    // in the same order, so all hold identical sums); (3) every thread forms
+    // the Householder scalars of column j and applies H_j to its own rows of
+    // its column.  Columns stay unscaled (v_j = scale_j * P(:, j) below row j)
+    // until the write-back.
     using LY = PanelLayout<B>;
     constexpr int TPC = LY::TPC, L = LY::L, WPC = LY::WPC;
-    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-    T *smem = (T *)smem_raw;
-    const int ldp = chunk + 16;   // columns 32 banks apart: the two half-waves of a read do not collide
-    T *Ps = smem;                 // Ps[q * ldp + i]: panel column q, local row i
-    T *scr = Ps + B * ldp;        // WPC * B partial sums (narrow panels)
+    constexpr int CH = PanelRows<B>::CH, R = PanelRows<B>::R;
+    constexpr int NWV = PANEL_THREADS / 64;
+    __shared__ T colbuf[CH];            // pivot column, local rows
+    __shared__ T scr[PANEL_THREADS];    // partial sums being combined
+    __shared__ T Ts[B * B];             // T factor (workgroup 0)
     __shared__ T hsh[B];
     __shared__ T topsh[B];
     __shared__ T scales[B];
     __shared__ T betas[B];
 
-    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t r0 = (int64_t)g * chunk;
     const int rows = (int)((m - r0) < chunk ? (m - r0) : chunk);
     const int nr = (int)(m < B ? m : B);
     const int cq = LY::col(tid), sub = LY::sub(tid);
 
-    for (int e = tid; e < rows * B; e += PANEL_THREADS) {
-        const int i = e % rows, q = e / rows;
-        Ps[q * ldp + i] = P[(r0 + i) + (int64_t)q * lda];
+    T x[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int i = sub + TPC * t;
+        x[t] = (i < rows) ? P[(r0 + i) + (int64_t)cq * lda] : (T)0;
     }
-    __syncthreads();
 
     for (int j = 0; j < nr; ++j) {
         const int E = epoch0 + j + 1;
         T *rec = part + (size_t)(j & 1) * PANEL_MAX_WGS * 2 * B;
-        // ---- (1) partial sums of column cq against column j over local rows below j
-        T acc = 0.0;
-        {
-            const int i0 = (int)((j + 1 - r0) > 0 ? (j + 1 - r0) : 0);  // first local row below j
-            const T *pj = Ps + j * ldp, *pq = Ps + cq * ldp;
-#pragma unroll 4
-            for (int i = i0 + sub; i < rows; i += TPC) acc += pj[i] * pq[i];
+        const int jl = (int)(j - r0);  // local index of row j (meaningful in workgroup 0)
+        // ---- (1) pivot column to LDS, partial sums of column cq against it
+        // (rows past the slice hold zeros in x, and so in colbuf: no row tests)
+        if (cq == j) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) colbuf[sub + TPC * t] = x[t];
+        }
+        __syncthreads();
+        // only the first TB register rows can hold a row <= j (local rows
+        // 0 .. B-1 of workgroup 0); the others are below j in every workgroup
+        constexpr int TB = (B + TPC - 1) / TPC;
+        T acc = 0.0, topv = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int i = sub + TPC * t;
+            const T pr = colbuf[i] * x[t];
+            if (t < TB) {
+                acc += (i > jl) ? pr : (T)0;
+                topv = (i == jl) ? x[t] : topv;
+            } else {
+                acc += pr;
+            }
+            if ((t & 15) == 15) __builtin_amdgcn_sched_barrier(0);  // bound the LDS reads in flight (registers)
         }
         acc = lane_group_sum<L>(acc);
         if (WPC > 1) {
-            if (lane == 0) scr[cq * WPC + (tid >> 6) % WPC] = acc;
+            if (lane == 0) scr[cq * WPC + w % WPC] = acc;
             __syncthreads();
             acc = 0.0;
 #pragma unroll
-            for (int w = 0; w < WPC; ++w) acc += scr[cq * WPC + w];
+            for (int u = 0; u < WPC; ++u) acc += scr[cq * WPC + u];
         }
+        const bool holds_row_j = (g == 0) && (jl % TPC == sub) && (jl < rows);
         if (G == 1) {
-            // one workgroup holds the whole column
             if (sub == 0) hsh[cq] = acc;
-            if (tid < B) topsh[tid] = Ps[tid * ldp + j];
+            if (holds_row_j) topsh[cq] = topv;
         } else {
             if (sub == 0) st_coh(&rec[(size_t)g * 2 * B + cq], acc);
-            if (g == 0 && tid < B) st_coh(&rec[B + tid], Ps[tid * ldp + j]);  // row j lives in chunk 0
+            if (holds_row_j) st_coh(&rec[B + cq], topv);
             mem_drain();
             __syncthreads();
             if (tid == 0) st_coh(&flags[g], E);
             // ---- (2) wait for every record of this column, then sum them:
-            // a thread's records h = sub, sub + TPC, ... are all requested
-            // before the first is used, summed in that order, then across the
-            // column's threads as in (1)
+            // wavefront w reads records h = w, w + NWV, ... whole (lane q
+            // entry q, all loads requested before the first is used); the
+            // NWV partial sums per entry are added in wavefront order
             if (tid < G)
                 while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
             __syncthreads();
-            // records are read whole: wavefront w takes records
-            // h = w, w + NWV, ..., lane q their entry q (contiguous 8B x B
-            // loads, all requested before the first is used); the NWV
-            // partial sums per entry are then added in wavefront order
-            constexpr int NWV = PANEL_THREADS / 64;
-            constexpr int MAXR = (PANEL_MAX_WGS + NWV - 1) / NWV;
-            const int w = tid >> 6;
-            T s2 = 0.0;
             if (lane < B) {
-                T v[MAXR];
+                T s2 = 0.0;
+                for (int h0 = w; h0 < G; h0 += 4 * NWV) {  // four records in flight per wavefront
+                    T v[4];
 #pragma unroll
-                for (int u = 0; u < MAXR; ++u) {
-                    const int h = w + u * NWV;
-                    v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + lane]) : (T)0;
+                    for (int u = 0; u < 4; ++u) {
+                        const int h = h0 + u * NWV;
+                        v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + lane]) : (T)0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) s2 += v[u];
                 }
-#pragma unroll
-                for (int u = 0; u < MAXR; ++u) s2 += v[u];
                 scr[w * B + lane] = s2;
             }
             if (tid < B) topsh[tid] = ld_coh(&rec[B + tid]);
@@ -240,45 +262,49 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
         }
         // Y(:, q)^T v_j for q < j, with column q's own scale applied
         if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = scales[tid] * (topsh[tid] + scale * hsh[tid]);
-        if (tau != 0.0) {
-            // rows i >= j of columns q > j: P(i, q) -= v_i tau (v_j^T P(:, q))
-            const int ncols = B - j - 1;
-            const int i0 = (int)((j - r0) > 0 ? (j - r0) : 0);
-            const int nrow = rows - i0;
-            const T *pj = Ps + j * ldp;
-            for (int e = tid; e < nrow * ncols; e += PANEL_THREADS) {
-                const int i = i0 + e % nrow, q = j + 1 + e / nrow;
-                const T vi = (r0 + i == j) ? (T)1 : scale * pj[i];
-                const T cf = tau * (topsh[q] + scale * hsh[q]);
-                Ps[q * ldp + i] -= vi * cf;
+        if (tau != 0.0 && cq > j) {
+            // rows i >= j of column cq: P(i, cq) -= v_i tau (v_j^T P(:, cq))
+            const T cf = tau * (topsh[cq] + scale * hsh[cq]);
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const int i = sub + TPC * t;
+                const T v = (t >= TB) ? scale * colbuf[i] : ((i == jl) ? (T)1 : ((i > jl) ? scale * colbuf[i] : (T)0));
+                x[t] -= v * cf;
+                if ((t & 15) == 15) __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        __syncthreads();
-    }
-
-    // ---- write back: explicit Y into the panel of A and into the two
-    // accumulator slots of the outer block
-    for (int e = tid; e < rows * B; e += PANEL_THREADS) {
-        const int i = e % rows, q = e / rows;
-        const int64_t gi = r0 + i;
-        T y = 0.0;
-        if (q < nr) y = (gi > q) ? scales[q] * Ps[q * ldp + i] : (gi == q ? 1.0 : 0.0);
-        P[gi + (int64_t)q * lda] = y;
-        Y1[gi + (int64_t)q * ldy] = y;
-        Y2[gi + (int64_t)q * ldy] = y;
-    }
-    if (g != 0) return;
-    // R (upper trapezoid of the first nr rows) -> band storage
-    for (int e = tid; e < B * B; e += PANEL_THREADS) {
-        const int p = e % B, q = e / B;
-        if (p <= q) {
-            const T v = (p >= nr) ? 0.0 : ((p == q) ? betas[q] : Ps[q * ldp + p]);
-            AB[(B + p - q) + (j0 + q) * ldab] = v;
         }
     }
     __syncthreads();
-    // T factor in LDS (reuse the panel area), then out
-    T *Ts = smem;
+
+    // ---- write back: explicit Y into the panel of A and into the two
+    // accumulator slots of the outer block (the row index is recomputed
+    // from an opaque copy, so the load's addresses are not kept alive in
+    // registers across the column loop)
+    int sub2 = sub;
+    asm volatile("" : "+v"(sub2));
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int i = sub2 + TPC * t;
+        if (i < rows) {
+            const int64_t gi = r0 + i;
+            T y = 0.0;
+            if (cq < nr) y = (gi > cq) ? scales[cq] * x[t] : (gi == cq ? (T)1 : (T)0);
+            P[gi + (int64_t)cq * lda] = y;
+            Y1[gi + (int64_t)cq * ldy] = y;
+            Y2[gi + (int64_t)cq * ldy] = y;
+        }
+    }
+    if (g != 0) return;
+    // R (upper trapezoid of the first nr rows) -> band storage
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int p = sub + TPC * t;
+        if (p < B && p <= cq) {
+            const T v = (p >= nr) ? (T)0 : ((p == cq) ? betas[cq] : x[t]);
+            AB[(B + p - cq) + (j0 + cq) * ldab] = v;
+        }
+    }
+    // T factor in LDS, then out
     for (int e = tid; e < B * B; e += PANEL_THREADS) Ts[e] = 0.0;
     __syncthreads();
     // column j: T[0:j, j] = -tau_j T[0:j, 0:j] Sg[0:j, j]; row p of the
@@ -286,12 +312,12 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     for (int j = 0; j < B; ++j) {
         const T tj = (j < nr) ? taus[j] : 0.0;
         if (TPC <= 64) {
-            const int p = tid / TPC, u = tid % TPC;
+            const int pr = tid / TPC, u = tid % TPC;
             T s = 0.0;
-            if (p < j)
-                for (int r = p + u; r < j; r += TPC) s += Ts[p + r * B] * Sg[r + (int64_t)j * B];
+            if (pr < j)
+                for (int r = pr + u; r < j; r += TPC) s += Ts[pr + r * B] * Sg[r + (int64_t)j * B];
             s = lane_group_sum<(TPC <= 64 ? TPC : 64)>(s);
-            if (p < j && u == 0) Ts[p + j * B] = -tj * s;
+            if (pr < j && u == 0) Ts[pr + j * B] = -tj * s;
         } else if (tid < j) {
             T s = 0.0;
             for (int r = tid; r < j; ++r) s += Ts[tid + r * B] * Sg[r + (int64_t)j * B];
@@ -308,25 +334,23 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T 
                           T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
 {
     // about PANEL_WGS workgroups (every one reads every record, so the
-    // traffic per column grows as G^2), more when a chunk would not fit in LDS
+    // traffic per column grows as G^2), fewer rows per workgroup than the
+    // registers hold, and workgroup 0 holds rows 0 .. B-1
+    constexpr int TPC = PanelLayout<B>::TPC;
+    constexpr int CH = PanelRows<B>::CH;
     int maxg = PANEL_WGS;
     if (ctx->panel_wgs > 0 && ctx->panel_wgs < maxg) maxg = (int)ctx->panel_wgs;
     int64_t chunk = evd_ceil_div(m, maxg);
-    const int64_t lds_rows = (140 * 1024 / (int64_t)sizeof(T) - PANEL_THREADS) / B - 16;
-    if (chunk > lds_rows) chunk = lds_rows;
     if (chunk < B) chunk = B;
-    chunk = evd_ceil_div(chunk, 32) * 32;
-    if (evd_ceil_div(m, chunk) > PANEL_MAX_WGS) chunk = evd_ceil_div(evd_ceil_div(m, PANEL_MAX_WGS), 32) * 32;
-    int G = (int)evd_ceil_div(m, chunk);
-    // LDS: B columns of chunk + 16 rows plus the narrow-panel partial sums
-    const int64_t ldp = chunk + 16;
-    size_t lds = (size_t)(B * ldp + PANEL_THREADS) * sizeof(T);
-    if (lds < (size_t)B * B * sizeof(T)) lds = (size_t)B * B * sizeof(T);
-    if (lds > 150 * 1024) return EVD_ERR_INVALID_ARG;
+    chunk = evd_ceil_div(chunk, TPC) * TPC;
+    if (chunk > CH) chunk = CH;
+    const int64_t G = evd_ceil_div(m, chunk);
+    if (G > PANEL_MAX_WGS) return EVD_ERR_INVALID_ARG;  // m > PANEL_MAX_WGS * CH rows
+    const size_t lds = 0;
     int chunk_i = (int)chunk;
     void *args[] = {&m, &chunk_i, &P, (void *)&lda, &Y1, &Y2, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
                     (void *)&ldab, (void *)&j0, &bar, &epoch0};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3(G), dim3(PANEL_THREADS), args,
+    hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3((unsigned)G), dim3(PANEL_THREADS), args,
                                               (unsigned)lds, ctx->stream);
     return evd_hip(ctx, e);
 }
