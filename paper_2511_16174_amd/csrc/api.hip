@@ -173,7 +173,7 @@ evd_status_t evd_dgemm(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_t m
     if (oa == OP_S && lower_c) { ctx->last_invalid_arg = 4; return EVD_ERR_INVALID_ARG; }
     if (ctx->device < 0) return EVD_ERR_HIP;
     EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
-    return gemm_f64(ctx->stream, oa, ob, lower_c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double *)work,
+    return gemm_f64(ctx->stream, oa, ob, lower_c ? 1 : 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double *)work,
                     work ? work_bytes / sizeof(double) : 0);
 }
 

@@ -173,6 +173,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f32x3_kernel(
                     float *cp = &C[gi + gj * ldc];
                     if (beta != 0.0f) v += beta * (*cp);
                     *cp = v;
+                    if (LOWER == 2 && gi > gj) C[gj + gi * ldc] = v;  // mirror into the upper triangle
                 }
             }
         }
@@ -216,6 +217,7 @@ void launch_ops3(hipStream_t s, int opa, int opb, int lower, dim3 grid, int64_t 
     EVD_G3_CASE(OP_S, OP_N, 0)
     EVD_G3_CASE(OP_N, OP_T, 1)
     EVD_G3_CASE(OP_N, OP_N, 1)
+    EVD_G3_CASE(OP_N, OP_T, 2)
 #undef EVD_G3_CASE
 }
 
@@ -270,8 +272,10 @@ evd_status_t gemm_f32x3(hipStream_t s, int opa, int opb, int lower_c, int64_t m,
         return evd_check_last();
     }
     if (!evd_gemm_ld_ok(lda) || !evd_gemm_ld_ok(ldb)) return EVD_ERR_INVALID_ARG;  // slice loader offsets
-    Plan3 p = plan3(m, n, k, ws ? ws_elems : 0);
-    const int lower = lower_c ? 1 : 0;
+    // lower_c 2: lower triangle computed and mirrored (see gemm_f64)
+    const int lower = (lower_c == 2) ? 2 : (lower_c ? 1 : 0);
+    if (lower == 2 && (m != n || opa != OP_N || opb != OP_T)) return EVD_ERR_INVALID_ARG;
+    Plan3 p = plan3(m, n, k, (ws && lower != 2) ? ws_elems : 0);
     dim3 grid((unsigned)evd_ceil_div(m, p.bm), (unsigned)evd_ceil_div(n, p.bn), (unsigned)p.splits);
     float *Cout = C;
     int64_t ldo = ldc, sstride = 0;
@@ -337,7 +341,7 @@ evd_status_t evd_sgemm_x3(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_
     if (bad) return EVD_ERR_INVALID_ARG;
     if (ctx->device < 0) return EVD_ERR_HIP;
     EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
-    return gemm_f32x3(ctx->stream, oa, ob, lower_c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (float *)work,
+    return gemm_f32x3(ctx->stream, oa, ob, lower_c ? 1 : 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (float *)work,
                       work ? work_bytes / sizeof(float) : 0);
 }
 

@@ -179,6 +179,7 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
                     double v = alpha * acc[i][j][r];
                     if (beta != 0.0) v += beta * (*cp);
                     *cp = v;
+                    if (LOWER == 2 && gi > gj) C[gj + gi * ldc] = v;  // mirror into the upper triangle
                 }
             }
         }
@@ -284,6 +285,7 @@ void launch_ops(hipStream_t s, int opa, int opb, int lower, dim3 grid, int64_t m
     EVD_GEMM_CASE(OP_N, OP_T, 1)
     EVD_GEMM_CASE(OP_T, OP_N, 1)
     EVD_GEMM_CASE(OP_T, OP_T, 1)
+    EVD_GEMM_CASE(OP_N, OP_T, 2)
 #undef EVD_GEMM_CASE
 }
 
@@ -357,8 +359,12 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         return evd_check_last();
     }
     if (!evd_gemm_ld_ok(lda) || !evd_gemm_ld_ok(ldb)) return EVD_ERR_INVALID_ARG;  // slice loader offsets
-    GemmPlan p = plan_gemm(m, n, k, ws ? ws_elems : 0);
-    const int lower = lower_c ? 1 : 0;
+    // lower_c: 0 full C, 1 lower triangle only, 2 lower triangle computed and
+    // also written transposed into the upper triangle (square C, op N/T, no
+    // K splitting)
+    const int lower = (lower_c == 2) ? 2 : (lower_c ? 1 : 0);
+    if (lower == 2 && (m != n || opa != OP_N || opb != OP_T)) return EVD_ERR_INVALID_ARG;
+    GemmPlan p = plan_gemm(m, n, k, (ws && lower != 2) ? ws_elems : 0);
     dim3 grid((unsigned)evd_ceil_div(m, p.bm), (unsigned)evd_ceil_div(n, p.bn), (unsigned)p.splits);
     double *Cout = C;
     int64_t ldo = ldc, sstride = 0;

@@ -533,9 +533,9 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
         // A_2 <- A_2 - [Y Z ...] [Z Y ...]^T on the lower triangle, rank 2 qe b
         const int64_t iK = (K0 + qe - 1) * b + b, rK = iK - base, mK = n - iK;
         if (mK > 0) {
-            EVD_CHECK(gemm_t(s, OP_N, OP_T, 1, mK, mK, 2 * qe * b, (T)-1, w.YZ + rK, ldc, w.ZY + rK, ldc, (T)1,
+            // (written into both triangles: the next block's A_2 W reads the full trailing matrix)
+            EVD_CHECK(gemm_t(s, OP_N, OP_T, 2, mK, mK, 2 * qe * b, (T)-1, w.YZ + rK, ldc, w.ZY + rK, ldc, (T)1,
                              A + iK + iK * lda, lda, (T *)nullptr, 0));
-            if (K0 + qe < p) mirror(iK + b);  // the next block's trailing matrix
         }
     }
     {
