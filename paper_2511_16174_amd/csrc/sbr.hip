@@ -387,10 +387,12 @@ struct SbrWork {
     int64_t q;  // panels per outer block
 };
 
-// Outer block of SBR: SBR_NB columns (at least one panel).
+// Outer block of SBR: SBR_NB columns by default (at least one panel); the
+// accumulators are sized for up to SBR_NB_MAX ("sbr_nb" may ask for more).
 constexpr int64_t SBR_NB = 256;
+constexpr int64_t SBR_NB_MAX = 512;
 
-inline int64_t sbr_panels_per_block(int64_t b) { return (SBR_NB / b) > 0 ? SBR_NB / b : 1; }
+inline int64_t sbr_panels_per_block(int64_t b) { return (SBR_NB_MAX / b) > 0 ? SBR_NB_MAX / b : 1; }
 
 template <typename T>
 size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
@@ -484,7 +486,8 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
     };
     mirror(b);
     const int64_t p = evd_sbr_num_panels(n, b);
-    const int64_t q = (ctx->sbr_nb > 0) ? ((ctx->sbr_nb / b) > 0 ? ctx->sbr_nb / b : 1) : w.q;
+    const int64_t q = (ctx->sbr_nb > 0) ? ((ctx->sbr_nb / b) > 0 ? ctx->sbr_nb / b : 1)
+                                        : ((SBR_NB / b) > 0 ? SBR_NB / b : 1);
     const int64_t qmax = w.q < q ? w.q : q;  // the accumulators hold w.q panels
     for (int64_t K0 = 0; K0 < p; K0 += qmax) {
         const int64_t qe = (K0 + qmax <= p) ? qmax : p - K0;
