@@ -18,11 +18,13 @@
 // them, with every earlier sweep.  Step (c, s) may therefore run as soon as
 // sweep c-1 has finished step s+1 (or all of its steps).
 //
-// Execution: one persistent launch; a workgroup of four threads per window
+// Execution: one persistent launch; a workgroup of sixteen threads per window
 // row owns sweeps c = g, g+P, g+2P, ... and stages each step's E and D windows
 // in LDS.  All band loads of a step are issued together (one memory latency
-// per step), row and column products run as quad-parallel dot products
-// reduced with DPP, and the Householder vector is formed by one wavefront.
+// per step), row and column products are split over the sixteen adjacent
+// lanes of a row and reduced with lane shuffles (the step's latency is on the
+// critical path of the sweep pipeline, so the work is spread as widely as a
+// workgroup allows), and the Householder vector is formed by one wavefront.
 // Band entries are read and written with device-coherent (sc1) accesses;
 // progress counters prog[c] (steps finished) are published after every
 // wavefront's stores have drained and polled the same way, so no step needs a
@@ -66,8 +68,18 @@ __device__ __forceinline__ void bc_house(T x, int lane, int m, T *v, T *tau, T *
     *v = (lane == 0) ? 1.0 : ((lane < m) ? x * scale : 0.0);
 }
 
-// Threads per workgroup: four per window row (at least one wavefront).
-__host__ __device__ constexpr int bc_threads(int B) { return 4 * B < 64 ? 64 : 4 * B; }
+// Threads per workgroup: sixteen per window row (at least one wavefront).
+__host__ __device__ constexpr int bc_threads(int B) { return 16 * B < 64 ? 64 : 16 * B; }
+
+// Sum over the RT adjacent lanes that share a window row (RT a power of two
+// dividing 64); every lane of the group ends with the same bits.
+template <int RT, typename T>
+__device__ __forceinline__ T row_sum(T v)
+{
+#pragma unroll
+    for (int off = RT / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
 
 template <int B, typename T>
 __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int64_t ldab, T *V, T *TAU,
@@ -87,7 +99,8 @@ __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int
 
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
-    const int p = t >> 2, rho = t & 3;  // quad-parallel phases: row (or column) p, quarter rho
+    constexpr int RT = NT / B;          // threads per row in the row (column) phases
+    const int p = t / RT, rho = t % RT;  // row (or column) p, part rho
     const bool own = p < B;
     for (int e = t; e < B * LDW; e += NT) {
         Es[e] = (T)0;
@@ -146,14 +159,14 @@ __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int
             __syncthreads();
 
             if (s > 0) {
-                // E receives H_{s-1} from the right: row p, columns q = rho (mod 4)
+                // E receives H_{s-1} from the right: row p, columns q = rho (mod RT)
                 if (tprev != 0.0) {
                     T y = 0.0;
                     if (own)
-                        for (int q = rho; q < B; q += 4) y += Es[p * LDW + q] * vps[q];
-                    y = quad_sum(y) * tprev;
+                        for (int q = rho; q < B; q += RT) y += Es[p * LDW + q] * vps[q];
+                    y = row_sum<RT>(y) * tprev;
                     if (own)
-                        for (int q = rho; q < B; q += 4) Es[p * LDW + q] -= y * vps[q];
+                        for (int q = rho; q < B; q += RT) Es[p * LDW + q] -= y * vps[q];
                     __syncthreads();
                 }
                 if (wv == 0) x = (lane < m) ? Es[lane * LDW + 0] : (T)0;
@@ -173,14 +186,14 @@ __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int
             const T tau = sh_tb[0], beta = sh_tb[1];
 
             if (s > 0) {
-                // H_s from the left on E's columns 1..B-1: column p, rows i = rho (mod 4)
+                // H_s from the left on E's columns 1..B-1: column p, rows i = rho (mod RT)
                 if (tau != 0.0) {
                     T w = 0.0;
                     if (own && p >= 1)
-                        for (int i = rho; i < B; i += 4) w += vs[i] * Es[i * LDW + p];
-                    w = quad_sum(w) * tau;
+                        for (int i = rho; i < B; i += RT) w += vs[i] * Es[i * LDW + p];
+                    w = row_sum<RT>(w) * tau;
                     if (own && p >= 1)
-                        for (int i = rho; i < B; i += 4) Es[i * LDW + p] -= vs[i] * w;
+                        for (int i = rho; i < B; i += RT) Es[i * LDW + p] -= vs[i] * w;
                     __syncthreads();
                 }
 #pragma unroll
@@ -196,8 +209,8 @@ __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int
             if (tau != 0.0) {
                 T u = 0.0;
                 if (own)
-                    for (int q = rho; q < B; q += 4) u += Ds[p * LDW + q] * vs[q];
-                u = quad_sum(u) * tau;
+                    for (int q = rho; q < B; q += RT) u += Ds[p * LDW + q] * vs[q];
+                u = row_sum<RT>(u) * tau;
                 const T vp = own ? vs[p] : (T)0;
                 const T a = wave_sum((own && rho == 0 && p < m) ? u * vp : (T)0);
                 if (lane == 0) red[wv] = a;
