@@ -80,6 +80,24 @@ __device__ __forceinline__ T row_sum(T v)
     for (int off = RT / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+// sixteen lanes, FP64: DPP within a row of 16 (lane ^ 1, lane ^ 2, half-row
+// mirror, row mirror), each step pairing lanes symmetrically
+template <int CTRL>
+__device__ __forceinline__ double dpp_pair(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true),
+                            __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true));
+}
+template <>
+__device__ __forceinline__ double row_sum<16, double>(double v)
+{
+    v += dpp_pair<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_pair<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_pair<0x141>(v);  // row_half_mirror
+    v += dpp_pair<0x140>(v);  // row_mirror
+    return v;
+}
 
 template <int B, typename T>
 __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int64_t ldab, T *V, T *TAU,
@@ -211,21 +229,25 @@ __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int
                 if (own)
                     for (int q = rho; q < B; q += RT) u += Ds[p * LDW + q] * vs[q];
                 u = row_sum<RT>(u) * tau;
-                const T vp = own ? vs[p] : (T)0;
-                const T a = wave_sum((own && rho == 0 && p < m) ? u * vp : (T)0);
-                if (lane == 0) red[wv] = a;
+                if (own && rho == 0) ws[p] = (p < m) ? u : (T)0;  // u (rows past m: zero)
+                // (tau/2) u.v: the rows of a wavefront combined by lane
+                // shuffles, the wavefronts' parts added by every thread in the
+                // same order; w = u - al v is then formed where it is used
+                T aw = (own && p < m) ? u * vs[p] : (T)0;
+#pragma unroll
+                for (int off = RT; off < 64; off <<= 1) aw += __shfl_xor(aw, off, 64);
+                if (lane == 0) red[wv] = aw;
                 __syncthreads();
                 T al = 0.0;
 #pragma unroll
                 for (int k = 0; k < NW; ++k) al += red[k];
                 al *= (T)0.5 * tau;
-                if (own && rho == 0) ws[p] = u - al * vp;
-                __syncthreads();
 #pragma unroll
                 for (int k = 0; k < KL; ++k) {
                     const int idx = k * NT + t, row = idx % B, col = idx / B;
                     if (col < m && row < m && row >= col) {
-                        const T d = Ds[row * LDW + col] - vs[row] * ws[col] - ws[row] * vs[col];
+                        const T wr = ws[row] - al * vs[row], wc = ws[col] - al * vs[col];
+                        const T d = Ds[row * LDW + col] - vs[row] * wc - wr * vs[col];
                         st_coh(Db + ((row - col) + col * ld), d);
                     }
                 }
