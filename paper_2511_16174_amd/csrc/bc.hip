@@ -46,31 +46,6 @@ __device__ __forceinline__ int64_t bc_steps(int64_t n, int64_t c, int b)
     return rem < 0 ? 0 : rem / b + 1;
 }
 
-// Householder vector of x[0:m) held one entry per lane (lanes >= m hold 0):
-// returns v (v[0] = 1) in the lane's slot, tau and beta.
-template <typename T>
-__device__ __forceinline__ void bc_house(T x, int lane, int m, T *v, T *tau, T *beta)
-{
-    const T x0 = __shfl(x, 0, 64);
-    const T tail = (lane >= 1 && lane < m) ? x * x : 0.0;
-    const T sig = wave_sum(tail);
-    if (sig == 0.0 || m <= 1) {
-        *tau = 0.0;
-        *beta = x0;
-        *v = (lane == 0) ? 1.0 : 0.0;
-        return;
-    }
-    const T nrm = sqrt(x0 * x0 + sig);
-    const T bt = (x0 >= 0.0) ? -nrm : nrm;
-    *tau = (bt - x0) / bt;
-    *beta = bt;
-    const T scale = 1.0 / (x0 - bt);
-    *v = (lane == 0) ? 1.0 : ((lane < m) ? x * scale : 0.0);
-}
-
-// Threads per workgroup: sixteen per window row (at least one wavefront).
-__host__ __device__ constexpr int bc_threads(int B) { return 16 * B < 64 ? 64 : 16 * B; }
-
 // Sum over the RT adjacent lanes that share a window row (RT a power of two
 // dividing 64); every lane of the group ends with the same bits.
 template <int RT, typename T>
@@ -98,6 +73,49 @@ __device__ __forceinline__ double row_sum<16, double>(double v)
     v += dpp_pair<0x140>(v);  // row_mirror
     return v;
 }
+
+// Sum over the 64 lanes of a wavefront, the same bits in every lane: DPP
+// within rows of 16, then the four row sums read from lanes 0, 16, 32, 48.
+__device__ __forceinline__ double bc_wave_sum(double v)
+{
+    v = row_sum<16, double>(v);
+    const double r0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 0));
+    const double r1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 16));
+    const double r2 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 32));
+    const double r3 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 48),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+__device__ __forceinline__ float bc_wave_sum(float v) { return wave_sum(v); }
+
+// Householder vector of x[0:m) held one entry per lane (lanes >= m hold 0):
+// returns v (v[0] = 1) in the lane's slot, tau and beta.
+template <typename T>
+__device__ __forceinline__ void bc_house(T x, int lane, int m, T *v, T *tau, T *beta)
+{
+    const T x0 = __shfl(x, 0, 64);
+    const T tail = (lane >= 1 && lane < m) ? x * x : 0.0;
+    const T sig = bc_wave_sum(tail);
+    if (sig == 0.0 || m <= 1) {
+        *tau = 0.0;
+        *beta = x0;
+        *v = (lane == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const T nrm = sqrt(x0 * x0 + sig);
+    const T bt = (x0 >= 0.0) ? -nrm : nrm;
+    *tau = (bt - x0) / bt;
+    *beta = bt;
+    const T scale = 1.0 / (x0 - bt);
+    *v = (lane == 0) ? 1.0 : ((lane < m) ? x * scale : 0.0);
+}
+
+// Threads per workgroup: sixteen per window row (at least one wavefront).
+__host__ __device__ constexpr int bc_threads(int B) { return 16 * B < 64 ? 64 : 16 * B; }
+
 
 template <int B, typename T>
 __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int64_t ldab, T *V, T *TAU,
