@@ -194,6 +194,9 @@ def main():
     ap.add_argument("--bcback-valu", type=int, default=0,
                     help="1 = reflector-by-reflector BC-back on the vector ALUs instead of the blocked MFMA kernel")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one plain 1 GiB device copy (the reference kernel for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     args = ap.parse_args()
@@ -201,6 +204,16 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.copy_calibration:
+        import torch
+        a = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+        b_ = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b_.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 1 << 30}), flush=True)
+        return
 
     if args.mode == "mixed":
         mixed_main(args)
