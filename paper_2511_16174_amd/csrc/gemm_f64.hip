@@ -327,13 +327,17 @@ GemmPlan plan_gemm(int64_t m, int64_t n, int64_t k, size_t ws_elems)
 evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob, int64_t max_m, int64_t max_n)
 {
     if (nprob <= 0 || max_m <= 0 || max_n <= 0) return EVD_OK;
-    if (nprob > 65535) return EVD_ERR_INVALID_ARG;
-    if (max_m > 64 && max_n > 64 && max_m * max_n >= (int64_t)512 * 128 * 128) {
-        dim3 grid((unsigned)evd_ceil_div(max_m, 128), (unsigned)evd_ceil_div(max_n, 128), (unsigned)nprob);
-        hipLaunchKernelGGL((gemm_f64_grouped_kernel<128, 128, 64, 32>), grid, dim3(512), 0, s, probs);
-    } else {
-        dim3 grid((unsigned)evd_ceil_div(max_m, 64), (unsigned)evd_ceil_div(max_n, 64), (unsigned)nprob);
-        hipLaunchKernelGGL((gemm_f64_grouped_kernel<64, 64, 32, 32>), grid, dim3(256), 0, s, probs);
+    // the problem index is the grid's z dimension (at most 65535 per launch)
+    constexpr int ZMAX = 65535;
+    for (int p0 = 0; p0 < nprob; p0 += ZMAX) {
+        const unsigned np = (unsigned)((nprob - p0) < ZMAX ? (nprob - p0) : ZMAX);
+        if (max_m > 64 && max_n > 64 && max_m * max_n >= (int64_t)512 * 128 * 128) {
+            dim3 grid((unsigned)evd_ceil_div(max_m, 128), (unsigned)evd_ceil_div(max_n, 128), np);
+            hipLaunchKernelGGL((gemm_f64_grouped_kernel<128, 128, 64, 32>), grid, dim3(512), 0, s, probs + p0);
+        } else {
+            dim3 grid((unsigned)evd_ceil_div(max_m, 64), (unsigned)evd_ceil_div(max_n, 64), np);
+            hipLaunchKernelGGL((gemm_f64_grouped_kernel<64, 64, 32, 32>), grid, dim3(256), 0, s, probs + p0);
+        }
     }
     return evd_check_last();
 }

@@ -109,3 +109,36 @@ def test_bisection_values_only(n, seed):
     w_ref = oracle.stev(d, e, jobz="N")
     assert np.all(np.diff(w) >= 0)
     assert M.eig_error(w, w_ref) <= 1e-14 * 8
+
+
+def test_dc_more_merges_than_one_launch_holds():
+    """n = 32800 has 16 merge levels; the deepest has 2^15 merges, i.e. 2^16
+    merge products, more than one launch's grid can index, so the grouped
+    products are issued in parts.  Checked against the closed-form spectrum of
+    the 1-D Laplacian and, on sampled columns, A z = lambda z and unit norm
+    (the full n x n eigenvector matrix is not copied to the host)."""
+    from paper_2511_16174_amd import evd
+    import torch
+    n = 32800
+    ctx = evd.context(0)
+    dd = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    de = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    dW = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dZ = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    wb = ctx.evd_dstedc_work_size("I", n)
+    work = work_dev(wb)
+    ctx.evd_dstedc("I", n, dd, de, dW, dZ, n, work, wb, info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    w = dW.cpu().numpy()
+    lam = W.laplacian_eigenvalues(n)
+    assert np.max(np.abs(w - lam)) <= 1e-12 * 4.0
+    Zt = dZ.view(n, n)  # row j of Zt = column j of Z
+    for j in (0, 1, n // 3, n // 2, n - 2, n - 1):
+        z = Zt[j].cpu().numpy()
+        Az = 2.0 * z
+        Az[1:] -= z[:-1]
+        Az[:-1] -= z[1:]
+        assert np.linalg.norm(Az - w[j] * z) <= 1e-12 * 4.0 * np.sqrt(n)
+        assert abs(np.linalg.norm(z) - 1.0) <= 1e-12 * n
