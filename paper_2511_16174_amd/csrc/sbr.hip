@@ -149,7 +149,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     constexpr int TPC = LY::TPC, L = LY::L, WPC = LY::WPC;
     constexpr int CH = PanelRows<B>::CH, R = PanelRows<B>::R;
     constexpr int NWV = PANEL_THREADS / 64;
-    __shared__ T colbuf[CH];            // pivot column, local rows
+    // pivot column, local rows; two buffers, since the owners of column j + 1
+    // write it while other wavefronts may still apply reflector j from column j
+    __shared__ T colbuf2[2][CH];
     __shared__ T scr[PANEL_THREADS];    // partial sums being combined
     __shared__ T Ts[B * B];             // T factor (workgroup 0)
     __shared__ T hsh[B];
@@ -174,6 +176,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
         const int E = epoch0 + j + 1;
         T *rec = part + (size_t)(j & 1) * PANEL_MAX_WGS * 2 * B;
         const int jl = (int)(j - r0);  // local index of row j (meaningful in workgroup 0)
+        T *colbuf = colbuf2[j & 1];
         // ---- (1) pivot column to LDS, partial sums of column cq against it
         // (rows past the slice hold zeros in x, and so in colbuf: no row tests)
         if (cq == j) {

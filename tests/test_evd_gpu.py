@@ -148,3 +148,46 @@ def test_blocked_bcback_matches_reflector_by_reflector(n, b, order):
     assert np.array_equal(w0, w1)
     assert np.abs(Q0 - Q1).max() <= 1e-12
     check(A, w0, Q0, oracle.syev(A, jobz="N"))
+
+
+@pytest.mark.parametrize("n", [32768])
+def test_full_size_sampled_pairs(n):
+    """The plain FP64 EVD with vectors at full size, in the configuration the
+    benchmark times (b = 64, A = (G + G^T)/(2 sqrt n) generated on the GPU):
+    48 sampled eigenpairs meet the residual gate column by column,
+    ||A x_j - w_j x_j||_2 / (n ||A||_2 eps) <= 10, are orthonormal against
+    every returned vector, and the eigenvalues keep the trace."""
+    import torch
+    from paper_2511_16174_amd import evd
+    dev = torch.device("cuda:0")
+    ctx = evd.context(0)
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    G = torch.randn((n, n), dtype=torch.float64, device=dev, generator=g)
+    A0 = (G + G.t()) * (0.5 / n ** 0.5)
+    del G
+    A = A0.clone()
+    w = torch.empty(n, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ctx.set_param("b", 64)
+    try:
+        wb = ctx.evd_dsyevd_work_size("V", "L", n, n)
+        work = torch.empty(wb // 8 + 64, dtype=torch.float64, device=dev)
+        ctx.evd_dsyevd("V", "L", n, A, n, w, work, wb, info)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_param("b", 0)
+    del work
+    assert int(info.item()) == 0
+    assert bool((w[1:] >= w[:-1]).all())
+    X = A.t()  # column-major eigenvectors: X[:, j]
+    J = torch.randperm(n, generator=torch.Generator().manual_seed(5))[:48].to(dev)
+    J[:3] = torch.tensor([0, n // 2, n - 1], device=dev)
+    Xs = X[:, J].contiguous()
+    norm2 = max(abs(w[0].item()), abs(w[-1].item()))
+    res = torch.linalg.norm(A0 @ Xs - Xs * w[J][None, :], dim=0) / (n * norm2 * M.EPS)
+    assert res.max().item() <= RES, res.max().item()
+    O = X.t() @ Xs
+    O[J, torch.arange(J.numel(), device=dev)] -= 1.0
+    assert torch.linalg.norm(O, dim=0).max().item() / (n * M.EPS) <= ORTH
+    assert abs(w.sum().item() - torch.trace(A0).item()) <= 1e-12 * n * norm2

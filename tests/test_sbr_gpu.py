@@ -103,3 +103,27 @@ def test_sbr_double_blocking_matches_single(n, b):
         Q = q_from_panels(Aout, T, n, b, p)
         rec = np.linalg.norm(Q @ B @ Q.T - A) / (n * np.linalg.norm(A) * M.EPS)
         assert rec <= 10
+
+
+@pytest.mark.parametrize("n,b,wgs", [(1100, 64, 1), (800, 32, 1)])
+def test_sbr_full_register_slices(n, b, wgs):
+    """Few panel workgroups ("panel_wgs"), so each holds the most rows its
+    registers take (512 per workgroup at b = 64): the per-column work is
+    longest there, as at the largest n.  The band and reflectors must still
+    reconstruct A, and two runs must agree bit for bit (every workgroup sums
+    the partial-sum records in one fixed order)."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    A = W.gaussian_sym(n, seed=n + wgs)
+    try:
+        ctx.set_param("panel_wgs", wgs)
+        AB1, Aout, T, p = run_sbr(A, b)
+        AB2, _, _, _ = run_sbr(A, b)
+    finally:
+        ctx.set_param("panel_wgs", 0)
+    assert np.array_equal(AB1, AB2)
+    B = band_to_dense(AB1, n, b, 2 * b + 1)
+    Q = q_from_panels(Aout, T, n, b, p)
+    assert M.orthogonality(Q) <= 10
+    rec = np.linalg.norm(Q @ B @ Q.T - A) / (n * np.linalg.norm(A) * M.EPS)
+    assert rec <= 10
