@@ -301,8 +301,9 @@ def main():
     else:
         roofline = None
 
+    what = "with eigenvectors" if args.jobz.upper() == "V" else "eigenvalues only"
     out = {
-        "metric": "EVD TFLOPS (4n^3/3) and time-to-solution, plain FP64 with eigenvectors",
+        "metric": f"EVD TFLOPS (4n^3/3) and time-to-solution, plain FP64 {what}",
         "value": round(value, 4),
         "unit": "TFLOPS",
         "n_gpus": 1,
@@ -317,7 +318,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"plain FP64 EVD with eigenvectors, n={n}, A=(G+G^T)/(2 sqrt n), G iid N(0,1)",
+        "config": {"workload": f"plain FP64 EVD {what}, n={n}, A=(G+G^T)/(2 sqrt n), G iid N(0,1)",
                    "n": n, "b": b, "jobz": args.jobz, "uplo": "L", "seed": 3,
                    "stage_order": "reordered" if args.order == 0 else "conventional"},
         "stage_ms": stages,
