@@ -72,9 +72,10 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *                  the matrix cores (b = 16, 32, 64)
  *   "bcback_group" sweeps per group of the blocked BC-back: 0 = automatic
  *                  (64 for b = 64, else 32), 32 = always 32
- *   "bcback_rows"  rows of Q per workgroup of the 64-sweep BC-back: 0 =
- *                  automatic (128 when that still gives every compute unit a
- *                  workgroup, else 64), 64 or 128
+ *   "bcback_rows"  rows of Q per workgroup of the 64-sweep BC-back: 64 or 128
+ *                  for all rows; 0 = automatic (128 for whole rounds of one
+ *                  workgroup per compute unit, a remainder of at most one
+ *                  round of 64-row workgroups as such, else 128)
  *   "orgsb_nb"     panels of b columns aggregated into one block reflector in
  *                  SBR-back, in columns (0 = 512)
  *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 256;

@@ -696,17 +696,39 @@ evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t 
     const int g = group_sweeps(ctx, b);
     const int64_t nblk = group_count(n, g);
     if (g == BC_GW) {
-        // 128-row workgroups (two wavefronts per SIMD) when they still fill
-        // every compute unit, else 64-row ones
-        const bool w8 = ctx->bcback_rows ? ctx->bcback_rows == 128 : mrows >= (int64_t)128 * ctx->num_cus;
-        const dim3 grid((unsigned)evd_ceil_div(mrows, w8 ? 128 : 64));
-#define EVD_BCW(NW, RV)                                                                                               hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, NW, RV>), grid, dim3(NW * 64), 0, s, mrows, n, V, Tg, nblk, Q,                        ldq);
-        if (w8) {
-            if (rev) { EVD_BCW(8, true) } else { EVD_BCW(8, false) }
+        // rows r0 .. r0 + rows - 1 with 128-row (two wavefronts per SIMD) or
+        // 64-row workgroups, one workgroup per compute unit at a time
+        auto launch = [&](bool w8, int64_t r0, int64_t rows) {
+            const dim3 grid((unsigned)evd_ceil_div(rows, w8 ? 128 : 64));
+            double *Qr = Q + r0;
+            if (w8) {
+                if (rev) hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 8, true>), grid, dim3(512), 0, s, rows, n, V,
+                                            Tg, nblk, Qr, ldq);
+                else hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 8, false>), grid, dim3(512), 0, s, rows, n, V,
+                                        Tg, nblk, Qr, ldq);
+            } else {
+                if (rev) hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 4, true>), grid, dim3(256), 0, s, rows, n, V,
+                                            Tg, nblk, Qr, ldq);
+                else hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 4, false>), grid, dim3(256), 0, s, rows, n, V,
+                                        Tg, nblk, Qr, ldq);
+            }
+        };
+        if (ctx->bcback_rows) {
+            launch(ctx->bcback_rows == 128, 0, mrows);
         } else {
-            if (rev) { EVD_BCW(4, true) } else { EVD_BCW(4, false) }
+            // A round of 64-row workgroups over every compute unit takes about
+            // 0.6 of a round of 128-row ones.  Whole rounds run with 128 rows;
+            // a remainder of at most one round of 64-row workgroups runs as
+            // such, a larger one as one more (partial) 128-row round.
+            const int64_t per8 = (int64_t)128 * ctx->num_cus, per4 = (int64_t)64 * ctx->num_cus;
+            const int64_t full = (mrows / per8) * per8, rem = mrows - full;
+            if (rem == 0 || rem > per4) {
+                launch(true, 0, mrows);
+            } else {
+                if (full > 0) launch(true, 0, full);
+                launch(false, full, rem);
+            }
         }
-#undef EVD_BCW
         return evd_check_last();
     }
     const dim3 grid((unsigned)evd_ceil_div(mrows, 64)), blk(256);

@@ -114,3 +114,30 @@ def test_bcback_b64_group_and_row_variants(trans, group, rows):
         ctx.set_param("bcback_rows", 0)
     out = from_dev(dX, mrows, n)
     assert np.max(np.abs(out - ref)) <= 100 * n * M.EPS * np.abs(X).max()
+
+
+@pytest.mark.parametrize("case", ["split", "two_rounds", "one_partial_round"])
+def test_bcback_b64_automatic_row_split(case):
+    """b = 64, automatic workgroup rows: whole rounds of 128-row workgroups
+    plus a tail of 64-row ones in a second launch ("split"), a tail too large
+    for that ("two_rounds"), and fewer rows than one round of 128-row
+    workgroups ("one_partial_round"); every row must match the reflector-by-
+    reflector product."""
+    from paper_2511_16174_amd import evd
+    import torch
+    ctx = evd.context(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    per8, per4 = 128 * cus, 64 * cus
+    mrows = {"split": per8 + 100, "two_rounds": per8 + per4 + 100, "one_partial_round": per4 + 50}[case]
+    n, b = 389, 64
+    B = random_band(n, b, seed=17)
+    d, e, V, TAU, steps = run_bc(B, b)
+    Qb = q_from_reflectors(n, b, V, TAU, steps)
+    X = W.rng(19).standard_normal((mrows, n))
+    ref = X @ Qb.T
+    dX = to_dev(X)
+    wb = ctx.evd_dbcback_work_size(n, b)
+    ctx.evd_dbcback("T", mrows, n, b, to_dev(V.reshape(-1)), to_dev(TAU.reshape(-1)), dX, mrows, work_dev(wb), wb)
+    torch.cuda.synchronize()
+    out = from_dev(dX, mrows, n)
+    assert np.max(np.abs(out - ref)) <= 100 * n * M.EPS * np.abs(X).max()
