@@ -66,7 +66,9 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "bc_waves"     number of persistent bulge-chasing wavefronts, 0 = automatic
  *   "order"        0 = reordered stages (paper Section 3.3), 1 = conventional order
  *   "timing"       1 = record per-stage times (host-synchronising; for benchmarks)
- *   "panel_wgs"    cap on the workgroups of one panel-QR launch, 0 = automatic
+ *   "panel_wgs"    0 (default) = each panel-QR workgroup holds as many rows
+ *                  as its registers take (512 at b = 64), the fewest
+ *                  workgroups; k > 0 = the rows spread over about k workgroups
  *   "bcback_valu"  1 = apply the bulge-chasing reflectors one by one on the
  *                  vector ALUs; 0 (default) = in compact-WY groups of sweeps on
  *                  the matrix cores (b = 16, 32, 64)

@@ -46,6 +46,7 @@ evd_status_t evd_create(evd_ctx_t *ctx, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return EVD_ERR_HIP; }
     c->num_cus = prop.multiProcessorCount;
+    gemm_set_cu_count(c->num_cus);
     for (int i = 0; i < 16; ++i) {
         if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete c; return EVD_ERR_HIP; }
     }

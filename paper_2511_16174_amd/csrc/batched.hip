@@ -156,7 +156,9 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
     // fork from `origin` onto the internal streams, join back into it
     auto enqueue = [&](hipStream_t origin) -> evd_status_t {
         ctx->bc_waves = (saved_bc > 0 && saved_bc < cap) ? saved_bc : cap;
-        ctx->panel_wgs = (saved_pw > 0 && saved_pw < cap) ? saved_pw : cap;
+        // panels take the fewest workgroups by default (ceil(m / 512) at b = 64,
+        // within the per-stream share for m <= 512 * cap)
+        ctx->panel_wgs = (saved_pw > 0 && saved_pw < cap) ? saved_pw : 0;
         ctx->timing = 0;
         evd_status_t st = EVD_OK;
         st = evd_hip(ctx, hipEventRecord(ctx->bev[ns], origin));

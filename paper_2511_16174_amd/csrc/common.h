@@ -161,7 +161,7 @@ struct evd_ctx_s {
     float stage_ms[8];
     // autotuned band width per size bucket (bucket = floor(log2 n)), 0 = none
     int64_t tuned_b[64];
-    int64_t panel_wgs;        // cap on panel-QR workgroups (0 = automatic)
+    int64_t panel_wgs;        // panel-QR rows spread over about this many workgroups (0 = fewest)
     int64_t sbr_nb;           // SBR outer block in columns (0 = 256; <= b: single blocking)
     int64_t orgsb_nb;         // SBR-back reflector group in columns (0 = 512)
     int64_t bcback_valu;      // 1 = reflector-by-reflector BC-back on the vector ALUs (0 = blocked MFMA)
@@ -225,6 +225,8 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
                       double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
                       double beta, double *C, int64_t ldc, double *splitk_ws, size_t splitk_ws_elems);
 size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k);
+// compute units the split-K planner fills (called when a context is created)
+void gemm_set_cu_count(int cus);
 // Row (within a 16 x 16 tile) held by lane group lq = lane/16, element r, of
 // the FP32 accumulator of v_mfma_f32_16x16x32_bf16.
 #define EVD_F32_MFMA_ROW(lq, r) (4 * (lq) + (r))

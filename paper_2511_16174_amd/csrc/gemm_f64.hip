@@ -28,6 +28,7 @@ namespace {
 constexpr int BK = 16;
 constexpr int PAD = 1;
 int g_gemm_swizzle = 1;  // XCD-aware tile order (gemm_tile); not used for triangular outputs, where it was slower
+int g_gemm_cus = 256;    // compute units of the device (set when a context is created)
 
 // waves per SIMD to budget registers for: 8-wavefront tiles (two workgroups
 // per CU, four waves per SIMD) fit 128 VGPRs, 4-wavefront tiles 256; the
@@ -307,13 +308,18 @@ GemmPlan plan_gemm(int64_t m, int64_t n, int64_t k, size_t ws_elems)
     }
     p.splits = 1;
     p.kchunk = k;
-    // split K when the output grid gives fewer than about three workgroups
-    // per compute unit and K is long
-    if (tiles < 768 && k >= 1024) {
-        int64_t want = evd_ceil_div(768, tiles);
-        int64_t maxs = k / 256;
-        int64_t sp = want < maxs ? want : maxs;
+    // Split K when the output grid fills under about one and a half rounds of
+    // the resident workgroups (two per CU for every tile shape) and K is long.
+    // Outputs of under one round (the SBR products m x b x m, W^T X, ...)
+    // take at least 8 splits and at least one full round of workgroups: the
+    // K-chunk of the narrow operand then stays in L2, and on m x 64 x m
+    // 8-16 splits beat the 2-5 that merely fill the CUs by up to 12 %.
+    const int64_t slots = 2 * (int64_t)g_gemm_cus;
+    if (tiles < (3 * slots) / 2 && k >= 1024) {
+        int64_t sp = (tiles < slots) ? evd_ceil_div(slots, tiles) : evd_ceil_div((3 * slots) / 2, tiles);
+        if (tiles < slots && sp < 8) sp = 8;
         if (sp > 64) sp = 64;
+        if (sp > k / 128) sp = k / 128;
         if (sp >= 2 && (size_t)(sp * m * n) <= ws_elems) {
             p.kchunk = evd_ceil_div(evd_ceil_div(k, sp), BK) * BK;
             p.splits = (int)evd_ceil_div(k, p.kchunk);
@@ -340,6 +346,11 @@ evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob
         }
     }
     return evd_check_last();
+}
+
+void gemm_set_cu_count(int cus)
+{
+    if (cus > 0) g_gemm_cus = cus;
 }
 
 size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k)

@@ -36,7 +36,6 @@ namespace {
 
 constexpr int PANEL_THREADS = 512;
 constexpr int PANEL_MAX_WGS = 256;  // workgroups of one panel launch (at most)
-constexpr int PANEL_WGS = 64;       // workgroups of one panel launch (target)
 
 template <typename T>
 __global__ void fill_kernel(T *p, int64_t count, T v)
@@ -336,17 +335,20 @@ template <int B, typename T>
 evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
                           T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
 {
-    // about PANEL_WGS workgroups (every one reads every record, so the
-    // traffic per column grows as G^2), fewer rows per workgroup than the
-    // registers hold, and workgroup 0 holds rows 0 .. B-1
+    // Automatic: as few workgroups as the registers allow (CH rows each):
+    // every workgroup reads every record of a column, so the exchange grows
+    // with G, and it costs more than the longer per-workgroup loops.  A cap
+    // "panel_wgs" spreads the rows over about that many workgroups instead.
+    // Workgroup 0 always holds rows 0 .. B-1.
     constexpr int TPC = PanelLayout<B>::TPC;
     constexpr int CH = PanelRows<B>::CH;
-    int maxg = PANEL_WGS;
-    if (ctx->panel_wgs > 0 && ctx->panel_wgs < maxg) maxg = (int)ctx->panel_wgs;
-    int64_t chunk = evd_ceil_div(m, maxg);
-    if (chunk < B) chunk = B;
-    chunk = evd_ceil_div(chunk, TPC) * TPC;
-    if (chunk > CH) chunk = CH;
+    int64_t chunk = CH;
+    if (ctx->panel_wgs > 0) {
+        chunk = evd_ceil_div(m, ctx->panel_wgs);
+        if (chunk < B) chunk = B;
+        chunk = evd_ceil_div(chunk, TPC) * TPC;
+        if (chunk > CH) chunk = CH;
+    }
     const int64_t G = evd_ceil_div(m, chunk);
     if (G > PANEL_MAX_WGS) return EVD_ERR_INVALID_ARG;  // m > PANEL_MAX_WGS * CH rows
     const size_t lds = 0;

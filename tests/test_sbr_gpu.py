@@ -105,13 +105,14 @@ def test_sbr_double_blocking_matches_single(n, b):
         assert rec <= 10
 
 
-@pytest.mark.parametrize("n,b,wgs", [(1100, 64, 1), (800, 32, 1)])
-def test_sbr_full_register_slices(n, b, wgs):
-    """Few panel workgroups ("panel_wgs"), so each holds the most rows its
-    registers take (512 per workgroup at b = 64): the per-column work is
-    longest there, as at the largest n.  The band and reflectors must still
-    reconstruct A, and two runs must agree bit for bit (every workgroup sums
-    the partial-sum records in one fixed order)."""
+@pytest.mark.parametrize("n,b,wgs", [(1100, 64, 0), (800, 32, 0), (1100, 64, 16)])
+def test_sbr_panel_row_slices(n, b, wgs):
+    """Panel workgroups holding the most rows their registers take (the
+    default, 512 rows at b = 64: the longest per-column work, as at the
+    largest n) or the rows spread over about 16 workgroups ("panel_wgs").
+    The band and reflectors must reconstruct A, and two runs must agree bit
+    for bit (every workgroup sums the partial-sum records in one fixed
+    order)."""
     from paper_2511_16174_amd import evd
     ctx = evd.context(0)
     A = W.gaussian_sym(n, seed=n + wgs)
