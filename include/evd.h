@@ -80,7 +80,7 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *                  round of 64-row workgroups as such, else 128)
  *   "orgsb_nb"     panels of b columns aggregated into one block reflector in
  *                  SBR-back, in columns (0 = 512)
- *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 256;
+ *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 320;
  *                  a value <= b gives single blocking (one update per panel)
  *   "last_hip_error" first HIP error code a call met (read; set 0 to clear)
  *   "capture_error"  HIP error that made the last batched graph capture fall
@@ -210,8 +210,9 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
  *      (unit lower trapezoidal: ones on its diagonal, zeros above); the rest
  *      of A (both triangles) is used as scratch.
  * The trailing updates are double-blocked (Section 4.1): deferred over outer
- * blocks of "sbr_nb" columns, with the trailing matrix mirrored into full
- * storage at the start of each block so that A_2 W is a plain product.
+ * blocks of "sbr_nb" columns, with the trailing matrix kept in full storage
+ * (each block's update writes both triangles) so that A_2 W is a plain
+ * product.
  *   T: the b x b upper triangular T_k of panel k at T + k*b*b (column-major,
  *      leading dimension b); evd_sbr_num_panels(n, b) panels.
  * Requires 1 <= b <= 64, b | 64 (b in {1,2,4,8,16,32,64}). */

@@ -162,7 +162,7 @@ struct evd_ctx_s {
     // autotuned band width per size bucket (bucket = floor(log2 n)), 0 = none
     int64_t tuned_b[64];
     int64_t panel_wgs;        // panel-QR rows spread over about this many workgroups (0 = fewest)
-    int64_t sbr_nb;           // SBR outer block in columns (0 = 256; <= b: single blocking)
+    int64_t sbr_nb;           // SBR outer block in columns (0 = 320; <= b: single blocking)
     int64_t orgsb_nb;         // SBR-back reflector group in columns (0 = 512)
     int64_t bcback_valu;      // 1 = reflector-by-reflector BC-back on the vector ALUs (0 = blocked MFMA)
     int64_t batch_streams;    // streams used by the batched driver (0 = 4)

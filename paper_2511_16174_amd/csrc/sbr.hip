@@ -394,7 +394,7 @@ struct SbrWork {
 
 // Outer block of SBR: SBR_NB columns by default (at least one panel); the
 // accumulators are sized for up to SBR_NB_MAX ("sbr_nb" may ask for more).
-constexpr int64_t SBR_NB = 256;
+constexpr int64_t SBR_NB = 320;
 constexpr int64_t SBR_NB_MAX = 512;
 
 inline int64_t sbr_panels_per_block(int64_t b) { return (SBR_NB_MAX / b) > 0 ? SBR_NB_MAX / b : 1; }
