@@ -210,6 +210,23 @@ __device__ __forceinline__ void gemm_tile(int swz, int &bx, int &by)
     by = r / gsz;
 }
 
+// Tile (bx >= by) of a lower-triangular grid launched as one dimension of
+// T (T + 1) / 2 workgroups: ids made XCD-contiguous as in gemm_tile, then
+// taken in row-major order of the lower triangle.
+__device__ __forceinline__ void gemm_tile_lower(int &bx, int &by)
+{
+    constexpr int XCD = 8;
+    const int total = gridDim.x;
+    int pid = blockIdx.x;
+    const int full = (total / XCD) * XCD;
+    if (pid < full) pid = (pid % XCD) * (total / XCD) + pid / XCD;
+    int i = (int)((sqrt(8.0 * (double)pid + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > pid) --i;
+    while ((i + 1) * (i + 2) / 2 <= pid) ++i;
+    bx = i;
+    by = pid - i * (i + 1) / 2;
+}
+
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, WM, WN, OPA)) void gemm_f64_kernel(
     int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
@@ -217,7 +234,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, 
     int64_t split_stride, int swz)
 {
     int bx, by;
-    gemm_tile(swz, bx, by);
+    if (LOWER && BM == BN && swz == 2) gemm_tile_lower(bx, by);  // triangular grid
+    else gemm_tile(swz, bx, by);
     const int64_t m0 = (int64_t)bx * BM, n0 = (int64_t)by * BN;
     if (LOWER && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
@@ -261,8 +279,16 @@ void launch_cfg(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64
                 int64_t split_stride)
 {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    // lower-triangular outputs of square tiles: a one-dimensional grid of the
+    // T (T + 1) / 2 tiles on or below the diagonal (no workgroups that exit)
+    int swz = LOWER ? 0 : g_gemm_swizzle;
+    if (LOWER && BM == BN && grid.z == 1 && m == n) {
+        const unsigned T = grid.x;
+        grid = dim3(T * (T + 1) / 2, 1, 1);
+        swz = 2;
+    }
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, OPA, OPB, LOWER>), grid, dim3(NT), 0, s, m, n, k, kchunk,
-                       alpha, A, lda, B, ldb, beta, C, ldc, split_stride, LOWER ? 0 : g_gemm_swizzle);
+                       alpha, A, lda, B, ldb, beta, C, ldc, split_stride, swz);
 }
 
 template <int BM, int BN, int WM, int WN>

@@ -9,13 +9,14 @@
 // outer block of q panels: the accumulators hold [Y_0 Z_0 Y_1 Z_1 ...] and
 // [Z_0 Y_0 Z_1 Y_1 ...], so any prefix of them is a consistent rank-2jb
 // update; each panel's columns are brought up to date just before its QR,
-// A_2 W is corrected for the deferred part, and one rank-2qb product on the
-// lower triangle per outer block updates the trailing matrix, which is then
-// mirrored into the upper triangle: inside the next block every A_2 W reads
-// the same stale full matrix with a plain (non-symmetric) product.
+// A_2 W is corrected for the deferred part, and one rank-2qb product per
+// outer block updates the trailing matrix: its lower triangle is computed and
+// every entry is stored in both triangles (the input is mirrored once at the
+// start), so inside the next block every A_2 W reads the same stale full
+// matrix with a plain (non-symmetric) product.
 //
 // Panel QR: the m x b panel is split into row chunks, one workgroup per chunk
-// holding its rows in LDS for the whole factorization.  Column j needs one
+// holding its rows in registers for the whole factorization.  Column j needs one
 // chip-wide reduction: every workgroup publishes the partial sums
 // h_q = sum_{i > j} P(i, j) P(i, q) for all q (its squared norm for q = j,
 // the dot products with the remaining columns for q > j and with the finished
