@@ -227,15 +227,15 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
             __syncthreads();
             if (lane < B) {
                 T s2 = 0.0;
-                for (int h0 = w; h0 < G; h0 += 4 * NWV) {  // four records in flight per wavefront
-                    T v[4];
+                for (int h0 = w; h0 < G; h0 += 8 * NWV) {  // eight records in flight per wavefront
+                    T v[8];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < 8; ++u) {
                         const int h = h0 + u * NWV;
                         v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + lane]) : (T)0;
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) s2 += v[u];
+                    for (int u = 0; u < 8; ++u) s2 += v[u];
                 }
                 scr[w * B + lane] = s2;
             }
