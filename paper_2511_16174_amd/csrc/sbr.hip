@@ -22,10 +22,10 @@
 // the dot products with the remaining columns for q > j and with the finished
 // reflectors for q < j), workgroup 0 adds row j; every workgroup waits for all
 // records, sums them in the same fixed order (so all hold bitwise identical
-// sums: one flag round trip per column), forms the Householder vector and
-// applies it to its rows.  Flags and data crossing workgroups use
-// device-coherent accesses; flags carry an epoch that grows across columns
-// and panels (nothing is reset between columns), and the records are double
+// sums), forms the Householder vector and applies it to its rows.  Records
+// cross workgroups through device-coherent accesses in a self-validating form
+// (each 64-bit word carries the column's epoch, which grows across columns
+// and panels; the buffer is cleared once per call), and they are double
 // buffered by column parity: a workgroup can only start writing column j+2
 // after every workgroup has published column j+1, i.e. has finished reading
 // column j.  The T factor (forward, column-wise: T[0:j, j] = -tau_j T[0:j, 0:j]
@@ -37,6 +37,69 @@ namespace {
 
 constexpr int PANEL_THREADS = 512;
 constexpr int PANEL_MAX_WGS = 256;  // workgroups of one panel launch (at most)
+
+// Panel partial-sum records cross workgroups in a self-validating form: every
+// 64-bit word carries 32 data bits and the 32-bit epoch of the column it
+// belongs to (a double takes two words, a float one), so a reader that sees
+// its epoch in every word of an entry has the whole value, without a flag and
+// without waiting for the writer's stores to drain.  64-bit device-coherent
+// stores and loads are single-copy atomic.
+template <typename T>
+constexpr int LL_WORDS = sizeof(T) == 8 ? 2 : 1;
+constexpr int LL_SPIN_MAX = 1 << 20;  // polls of an unwritten record before giving up (result poisoned)
+
+// uint64 words of the record buffer: two column parities x PANEL_MAX_WGS
+// records x 2b entries x (at most) two words
+inline size_t panel_part_words(int64_t b) { return (size_t)2 * PANEL_MAX_WGS * 2 * (size_t)b * 2; }
+
+__device__ __forceinline__ uint64_t ll_word(uint32_t bits, uint32_t epoch)
+{
+    return (uint64_t)bits | ((uint64_t)epoch << 32);
+}
+__device__ __forceinline__ uint32_t ll_epoch(uint64_t w) { return (uint32_t)(w >> 32); }
+
+template <typename T>
+__device__ __forceinline__ void ll_store(uint64_t *p, T v, uint32_t epoch)
+{
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        st_coh(p, ll_word((uint32_t)b, epoch));
+        st_coh(p + 1, ll_word((uint32_t)(b >> 32), epoch));
+    } else {
+        st_coh(p, ll_word(__builtin_bit_cast(uint32_t, v), epoch));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T ll_value(const uint64_t (&w)[LL_WORDS<T>])
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, (uint64_t)(uint32_t)w[0] | ((uint64_t)(uint32_t)w[1] << 32));
+    else
+        return __builtin_bit_cast(T, (uint32_t)w[0]);
+}
+
+// one entry, polled until every word carries `epoch` (NaN if it never does)
+template <typename T>
+__device__ __forceinline__ T ll_load(const uint64_t *p, uint32_t epoch)
+{
+    uint64_t w[LL_WORDS<T>];
+#pragma unroll
+    for (int q = 0; q < LL_WORDS<T>; ++q) w[q] = ld_coh(p + q);
+    for (int it = 0; it < LL_SPIN_MAX; ++it) {
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < LL_WORDS<T>; ++q) {
+            if (ll_epoch(w[q]) != epoch) {
+                ok = false;
+                w[q] = ld_coh(p + q);
+            }
+        }
+        if (ok) return ll_value<T>(w);
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return (T)__builtin_nan("");
+}
 
 template <typename T>
 __global__ void fill_kernel(T *p, int64_t count, T v)
@@ -130,18 +193,18 @@ template <int B, typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, T *P, int64_t lda,
                                                                  T *Y1, T *Y2, int64_t ldy, T *part,
                                                                  T *Sg, T *taus, T *Tout,
-                                                                 T *AB, int64_t ldab, int64_t j0, int *flags,
-                                                                 int epoch0)
+                                                                 T *AB, int64_t ldab, int64_t j0, int epoch0)
 {
     // Workgroup g holds rows r0 .. r0 + chunk - 1 of the m x B panel in
     // registers.  Per column j: (1) the owners of column j put it in LDS;
     // every thread forms its partial sums h_q = sum_{rows i > j} P(i, j) P(i, q)
     // for its column q; (2) the partial sums of all workgroups are combined
-    // (through records in device memory when G > 1:
-    // part[(j & 1) * PANEL_MAX_WGS * 2B + h * 2B + q] holds workgroup h's sums
-    // in [0, B) and, for h = 0, row j of the panel in [B, 2B); flags[h] is the
-    // epoch of the last column h published; every workgroup sums all records
-    // in the same order, so all hold identical sums); (3) every thread forms
+    // (through records in device memory when G > 1: entry q of record h,
+    // LL_WORDS words from ((j & 1) * PANEL_MAX_WGS * 2B + h * 2B + q) *
+    // LL_WORDS, holds workgroup h's sum for q < B and, for h = 0, row j of
+    // the panel for B <= q < 2B, tagged with column j's epoch; every
+    // workgroup sums all records in the same order, so all hold identical
+    // sums); (3) every thread forms
     // the Householder scalars of column j and applies H_j to its own rows of
     // its column.  Columns stay unscaled (v_j = scale_j * P(:, j) below row j)
     // until the write-back.
@@ -174,7 +237,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
 
     for (int j = 0; j < nr; ++j) {
         const int E = epoch0 + j + 1;
-        T *rec = part + (size_t)(j & 1) * PANEL_MAX_WGS * 2 * B;
+        uint64_t *rec = (uint64_t *)part + (size_t)(j & 1) * PANEL_MAX_WGS * 2 * B * LL_WORDS<T>;
         const int jl = (int)(j - r0);  // local index of row j (meaningful in workgroup 0)
         T *colbuf = colbuf2[j & 1];
         // ---- (1) pivot column to LDS, partial sums of column cq against it
@@ -213,33 +276,50 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
             if (sub == 0) hsh[cq] = acc;
             if (holds_row_j) topsh[cq] = topv;
         } else {
-            if (sub == 0) st_coh(&rec[(size_t)g * 2 * B + cq], acc);
-            if (holds_row_j) st_coh(&rec[B + cq], topv);
-            mem_drain();
-            __syncthreads();
-            if (tid == 0) st_coh(&flags[g], E);
-            // ---- (2) wait for every record of this column, then sum them:
-            // wavefront w reads records h = w, w + NWV, ... whole (lane q
-            // entry q, all loads requested before the first is used); the
-            // NWV partial sums per entry are added in wavefront order
-            if (tid < G)
-                while (ld_coh(&flags[tid]) < E) __builtin_amdgcn_s_sleep(1);
-            __syncthreads();
+            // records in the self-validating form of ll_store: no flags and
+            // no wait for the stores to land before others may read them
+            if (sub == 0) ll_store(&rec[((size_t)g * 2 * B + cq) * LL_WORDS<T>], acc, (uint32_t)E);
+            if (holds_row_j) ll_store(&rec[((size_t)B + cq) * LL_WORDS<T>], topv, (uint32_t)E);
+            if (WPC > 1) __syncthreads();  // scr was just read by the column reduction
+            // ---- (2) every record of this column, summed: wavefront w reads
+            // records h = w, w + NWV, ... whole (lane q entry q, eight records
+            // in flight, those not yet written polled again); the NWV partial
+            // sums per entry are added in wavefront order
             if (lane < B) {
                 T s2 = 0.0;
-                for (int h0 = w; h0 < G; h0 += 8 * NWV) {  // eight records in flight per wavefront
-                    T v[8];
+                for (int h0 = w; h0 < G; h0 += 8 * NWV) {
+                    uint64_t wd[8][LL_WORDS<T>];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const int h = h0 + u * NWV;
-                        v[u] = (h < G) ? ld_coh(&rec[(size_t)h * 2 * B + lane]) : (T)0;
+#pragma unroll
+                        for (int q = 0; q < LL_WORDS<T>; ++q)
+                            wd[u][q] = (h < G) ? ld_coh(&rec[((size_t)h * 2 * B + lane) * LL_WORDS<T> + q])
+                                               : ll_word(0u, (uint32_t)E);
+                    }
+                    bool ok = false;
+                    for (int it = 0; it < LL_SPIN_MAX && !ok; ++it) {
+                        ok = true;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int h = h0 + u * NWV;
+#pragma unroll
+                            for (int q = 0; q < LL_WORDS<T>; ++q) {
+                                if (ll_epoch(wd[u][q]) != (uint32_t)E) {
+                                    ok = false;
+                                    wd[u][q] = ld_coh(&rec[((size_t)h * 2 * B + lane) * LL_WORDS<T> + q]);
+                                }
+                            }
+                        }
+                        if (!ok) __builtin_amdgcn_s_sleep(1);
                     }
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) s2 += v[u];
+                    for (int u = 0; u < 8; ++u) s2 += ll_value<T>(wd[u]);
+                    if (!ok) s2 = (T)__builtin_nan("");  // never written: poison, do not hang
                 }
                 scr[w * B + lane] = s2;
             }
-            if (tid < B) topsh[tid] = ld_coh(&rec[B + tid]);
+            if (tid < B) topsh[tid] = ll_load<T>(&rec[((size_t)B + tid) * LL_WORDS<T>], (uint32_t)E);
             __syncthreads();
             if (tid < B) {
                 T r = 0.0;
@@ -334,7 +414,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
 
 template <int B, typename T>
 evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
-                          T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
+                          T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int epoch0)
 {
     // Automatic: as few workgroups as the registers allow (CH rows each):
     // every workgroup reads every record of a column, so the exchange grows
@@ -355,7 +435,7 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T 
     const size_t lds = 0;
     int chunk_i = (int)chunk;
     void *args[] = {&m, &chunk_i, &P, (void *)&lda, &Y1, &Y2, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
-                    (void *)&ldab, (void *)&j0, &bar, &epoch0};
+                    (void *)&ldab, (void *)&j0, &epoch0};
     hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3((unsigned)G), dim3(PANEL_THREADS), args,
                                               (unsigned)lds, ctx->stream);
     return evd_hip(ctx, e);
@@ -363,16 +443,16 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T 
 
 template <typename T>
 evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
-                            T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int *bar, int epoch0)
+                            T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int epoch0)
 {
     switch (b) {
-    case 1: return launch_panel<1, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 2: return launch_panel<2, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 4: return launch_panel<4, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 8: return launch_panel<8, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 16: return launch_panel<16, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 32: return launch_panel<32, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
-    case 64: return launch_panel<64, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, bar, epoch0);
+    case 1: return launch_panel<1, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
+    case 2: return launch_panel<2, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
+    case 4: return launch_panel<4, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
+    case 8: return launch_panel<8, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
+    case 16: return launch_panel<16, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
+    case 32: return launch_panel<32, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
+    case 64: return launch_panel<64, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
     default: return EVD_ERR_INVALID_ARG;
     }
 }
@@ -384,12 +464,11 @@ struct SbrWork {
     T *W;     // n x b
     T *M;     // b x b
     T *U;     // 2nb x b
-    T *part;  // reduction scratch of the panel kernel
+    T *part;  // partial-sum records of the panel kernel (uint64 words)
     T *Sg;    // b x b
     T *taus;  // b
     T *gemm_ws;
     size_t gemm_ws_elems;
-    int *bar;  // flags of the panel kernel
     int64_t q;  // panels per outer block
 };
 
@@ -417,7 +496,7 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     t.W = take((size_t)n * b);
     t.M = take((size_t)b * b);
     t.U = take((size_t)2 * nb * b);
-    t.part = take((size_t)2 * PANEL_MAX_WGS * 2 * b + 64);
+    t.part = take(panel_part_words(b) * sizeof(uint64_t) / sizeof(T));
     t.Sg = take((size_t)b * b);
     t.taus = take((size_t)b);
     // split-K workspace for the products with K = the trailing size m of each
@@ -431,7 +510,6 @@ size_t sbr_layout(int64_t n, int64_t b, char *base, SbrWork<T> *w)
     }
     t.gemm_ws = take(ws);
     t.gemm_ws_elems = ws;
-    t.bar = (int *)take((PANEL_MAX_WGS + 64) * sizeof(int) / sizeof(T));
     if (w) *w = t;
     return off;
 }
@@ -481,7 +559,10 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
         hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)(evd_ceil_div(cnt, 256) < 4096 ? evd_ceil_div(cnt, 256) : 4096)),
                            dim3(256), 0, s, AB, cnt, (T)0);
     }
-    hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(256), 0, s, w.bar, (int64_t)(PANEL_MAX_WGS + 1), 0);
+    // panel records start with epoch 0, which no column uses (records of an
+    // earlier call carry the same epochs and must not be taken for new ones)
+    hipLaunchKernelGGL(fill_kernel<unsigned long long>, dim3(64), dim3(256), 0, s, (unsigned long long *)w.part,
+                       (int64_t)panel_part_words(b), 0ull);
     // the trailing matrix is kept in full (both triangles) at the start of every
     // outer block, so A_2 W is a plain product over the stale matrix
     auto mirror = [&](int64_t i0) {
@@ -519,7 +600,7 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
             T *P = A + i0 + j0 * lda;
             T *A2 = A + i0 + i0 * lda;
             EVD_CHECK(panel_dispatch<T>(ctx, b, m, P, lda, Y, w.ZY + ro + (2 * t + 1) * b * ldc, ldc, w.part, w.Sg,
-                                        w.taus, Tk, AB, ldab, j0, w.bar, (int)(k * (b + 1))));
+                                        w.taus, Tk, AB, ldab, j0, (int)(k * (b + 1))));
             // W = Y T
             EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)1, Y, ldc, Tk, b, (T)0, w.W, m, (T *)nullptr, 0));
             // X = A_2 W (stale A_2 inside the block) into the Z slot
