@@ -273,6 +273,34 @@ __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const dou
     }
 }
 
+// Split-K sum for small outputs with many partials: SPL adjacent lanes of a
+// wavefront share one output entry, each adding the partials z = part,
+// part + SPL, ..., then the SPL sums are combined by lane shuffles (in a
+// fixed order: the result does not depend on the launch).
+template <int SPL>
+__global__ __launch_bounds__(256) void splitk_reduce_wide_kernel(int64_t m, int64_t n, int splits,
+                                                                 const double *__restrict__ P, int64_t stride,
+                                                                 double alpha, double beta, double *__restrict__ C,
+                                                                 int64_t ldc, int lower)
+{
+    const int64_t total = m * n;
+    const int part = threadIdx.x % SPL;
+    for (int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / SPL; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x / SPL) {
+        const int64_t i = idx % m, j = idx / m;
+        double s = 0.0;
+        for (int z = part; z < splits; z += SPL) s += P[z * stride + i + j * m];
+#pragma unroll
+        for (int off = SPL / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (part == 0 && !(lower && i < j)) {
+            double *cp = &C[i + j * ldc];
+            double v = alpha * s;
+            if (beta != 0.0) v += beta * (*cp);
+            *cp = v;
+        }
+    }
+}
+
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
 void launch_cfg(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha,
                 const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
@@ -344,7 +372,10 @@ GemmPlan plan_gemm(int64_t m, int64_t n, int64_t k, size_t ws_elems)
     if (tiles < (3 * slots) / 2 && k >= 1024) {
         int64_t sp = (tiles < slots) ? evd_ceil_div(slots, tiles) : evd_ceil_div((3 * slots) / 2, tiles);
         if (tiles < slots && sp < 8) sp = 8;
-        if (sp > 64) sp = 64;
+        // (outputs of a few tiles, W^T X or [Z Y]^T W in SBR, take up to 256
+        // splits: one workgroup per CU; their partial sums are few)
+        const int64_t smax = (tiles <= 4) ? 256 : 64;
+        if (sp > smax) sp = smax;
         if (sp > k / 128) sp = k / 128;
         if (sp >= 2 && (size_t)(sp * m * n) <= ws_elems) {
             p.kchunk = evd_ceil_div(evd_ceil_div(k, sp), BK) * BK;
@@ -431,10 +462,17 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
                                    sstride);
     EVD_CHECK(evd_check_last());
     if (p.splits > 1) {
-        int64_t blocks = evd_ceil_div(m * n, 256);
-        if (blocks > 65535) blocks = 65535;
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, n, p.splits, ws,
-                           sstride, alpha, beta, C, ldc, lower);
+        if (m * n <= 65536 && p.splits >= 16) {
+            // few entries, many partials: 16 lanes per entry
+            const int64_t blocks = evd_ceil_div(m * n * 16, 256);
+            hipLaunchKernelGGL(splitk_reduce_wide_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, s, m, n,
+                               p.splits, ws, sstride, alpha, beta, C, ldc, lower);
+        } else {
+            int64_t blocks = evd_ceil_div(m * n, 256);
+            if (blocks > 65535) blocks = 65535;
+            hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, n, p.splits, ws,
+                               sstride, alpha, beta, C, ldc, lower);
+        }
         EVD_CHECK(evd_check_last());
     }
     return EVD_OK;

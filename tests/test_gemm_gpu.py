@@ -77,3 +77,36 @@ def test_dgemm_no_workspace_equals_splitk():
         ctx.evd_dgemm("T", "N", 0, m, n, k, 1.0, dev(A), k, dev(B), k, 0.0, dC, m, work, wb)
         torch.cuda.synchronize()
         assert np.max(np.abs(host(dC, m, n) - ref)) <= 4 * k * 2.2e-16 * 20
+
+
+@pytest.mark.parametrize("m,n,k,opa,lower,alpha,beta", [(64, 64, 20000, "T", 1, 0.5, 2.0),
+                                                        (512, 64, 32768, "T", 0, -1.0, 1.0),
+                                                        (300, 64, 5000, "N", 0, 1.0, 0.5),
+                                                        (100, 3, 4096, "T", 0, 1.0, 0.0)])
+def test_dgemm_many_splits_small_outputs(m, n, k, opa, lower, alpha, beta):
+    """Small outputs with long K take many K splits (up to 256) and a split sum
+    shared by several lanes per entry; alpha, beta and the lower-triangle
+    mode apply to the summed product."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    rng = np.random.default_rng(m + k)
+    A = rng.standard_normal((k, m)) if opa == "T" else rng.standard_normal((m, k))
+    B = rng.standard_normal((k, n))
+    C0 = rng.standard_normal((m, n))
+    opA = A.T if opa == "T" else A
+    ref = alpha * (opA @ B) + beta * C0
+    dC = dev(C0)
+    wb = ctx.evd_dgemm_work_size(m, n, k)
+    assert wb > 0
+    work = torch.empty(wb // 8 + 1, dtype=torch.float64, device="cuda")
+    lda = k if opa == "T" else m
+    ctx.evd_dgemm(opa, "N", lower, m, n, k, alpha, dev(A), lda, dev(B), k, beta, dC, m, work, wb)
+    torch.cuda.synchronize()
+    out = host(dC, m, n)
+    tol = 4 * k * 2.2e-16 * np.abs(opA).max() * np.abs(B).max() * abs(alpha) * 4 + 1e-12
+    if lower:
+        mask = np.tril(np.ones((m, n), bool))
+        assert np.max(np.abs(out[mask] - ref[mask])) <= tol
+        assert np.array_equal(out[~mask], C0[~mask])
+    else:
+        assert np.max(np.abs(out - ref)) <= tol
