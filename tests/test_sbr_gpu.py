@@ -105,11 +105,13 @@ def test_sbr_double_blocking_matches_single(n, b):
         assert rec <= 10
 
 
-@pytest.mark.parametrize("n,b,wgs", [(1100, 64, 0), (800, 32, 0), (1100, 64, 16)])
+@pytest.mark.parametrize("n,b,wgs", [(1100, 64, 0), (800, 32, 0), (1100, 64, 16), (1100, 32, 16), (1100, 16, 16),
+                                     (300, 4, 8), (200, 1, 4)])
 def test_sbr_panel_row_slices(n, b, wgs):
     """Panel workgroups holding the most rows their registers take (the
     default, 512 rows at b = 64: the longest per-column work, as at the
-    largest n) or the rows spread over about 16 workgroups ("panel_wgs").
+    largest n) or the rows spread over several workgroups ("panel_wgs"),
+    also for narrow panels whose columns span several wavefronts (b <= 4).
     The band and reflectors must reconstruct A, and two runs must agree bit
     for bit (every workgroup sums the partial-sum records in one fixed
     order)."""
