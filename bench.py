@@ -202,7 +202,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU (no multi-GPU path); --gpus must be 1"}))
         sys.exit(2)
 
     if args.copy_calibration:
