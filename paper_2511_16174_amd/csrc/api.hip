@@ -63,6 +63,7 @@ evd_status_t evd_destroy(evd_ctx_t ctx)
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     for (int i = 0; i < ctx->nbstreams; ++i) (void)hipStreamDestroy(ctx->bstreams[i]);
     if (ctx->cstream) (void)hipStreamDestroy(ctx->cstream);
+    if (ctx->astream) (void)hipStreamDestroy(ctx->astream);
     for (int i = 0; i < 17; ++i)
         if (ctx->bev[i]) (void)hipEventDestroy(ctx->bev[i]);
     delete ctx;

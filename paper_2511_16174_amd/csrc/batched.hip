@@ -160,6 +160,7 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
         // within the per-stream share for m <= 512 * cap)
         ctx->panel_wgs = (saved_pw > 0 && saved_pw < cap) ? saved_pw : 0;
         ctx->timing = 0;
+        ctx->in_batch = 1;
         evd_status_t st = EVD_OK;
         st = evd_hip(ctx, hipEventRecord(ctx->bev[ns], origin));
         for (int k = 0; st == EVD_OK && k < ns; ++k) st = evd_hip(ctx, hipStreamWaitEvent(ctx->bstreams[k], ctx->bev[ns], 0));
@@ -180,6 +181,7 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
         ctx->bc_waves = saved_bc;
         ctx->panel_wgs = saved_pw;
         ctx->timing = saved_t;
+        ctx->in_batch = 0;
         return st;
     };
 

@@ -177,6 +177,8 @@ struct evd_ctx_s {
     int nbstreams;
     hipGraphExec_t gexec;
     uint64_t gkey;
+    int in_batch;             // 1 while the batched driver enqueues its matrices
+    hipStream_t astream;      // auxiliary stream: BC-back T factors formed beside D&C
 };
 
 // First failing HIP status seen on this host thread (internal helpers without

@@ -169,6 +169,21 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
         EVD_CHECK(dc_run(ctx, 'N', n, w.d, w.e, W, nullptr, 1, w.dc, info));
         mark(3);
     } else {
+        // conventional order: the BC-back T factors need only the reflectors,
+        // so they are formed on an auxiliary stream while D&C runs (not in
+        // the batched driver, whose streams are captured into a graph)
+        const bool blocked_c = ctx->order != 0 && w.Tg && ctx->bcback_valu == 0 && bcback_mfma_fits(n);
+        const bool ahead = blocked_c && !ctx->in_batch;
+        if (ahead) {
+            if (!ctx->astream) EVD_CHECK(evd_hip(ctx, hipStreamCreateWithFlags(&ctx->astream, hipStreamNonBlocking)));
+            EVD_CHECK(evd_hip(ctx, hipEventRecord(ctx->ev[8], s)));
+            EVD_CHECK(evd_hip(ctx, hipStreamWaitEvent(ctx->astream, ctx->ev[8], 0)));
+            ctx->stream = ctx->astream;
+            const evd_status_t st = bcback_mfma_prepare(ctx, n, b, w.V, w.TAU, w.Tg, true);
+            ctx->stream = s;
+            EVD_CHECK(st);
+            EVD_CHECK(evd_hip(ctx, hipEventRecord(ctx->ev[9], ctx->astream)));
+        }
         EVD_CHECK(dc_run(ctx, 'I', n, w.d, w.e, W, w.Qd, n, w.dc, info));
         mark(3);
         if (ctx->order == 0) {
@@ -190,8 +205,9 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
             // stage times: [3] transpose (+ group T factors), [4] BC-back alone,
             // [5] transpose + SBR-back + copy
             EVD_CHECK(transpose_run(s, n, w.Qd, n, w.Qs, n));
-            const bool blocked = w.Tg && ctx->bcback_valu == 0 && bcback_mfma_fits(n);
-            if (blocked) EVD_CHECK(bcback_mfma_prepare(ctx, n, b, w.V, w.TAU, w.Tg, true));
+            const bool blocked = blocked_c;
+            if (ahead) EVD_CHECK(evd_hip(ctx, hipStreamWaitEvent(s, ctx->ev[9], 0)));
+            else if (blocked) EVD_CHECK(bcback_mfma_prepare(ctx, n, b, w.V, w.TAU, w.Tg, true));
             mark(4);
             if (blocked)
                 EVD_CHECK(bcback_mfma_apply(ctx, n, n, b, w.V, w.Qs, n, w.Tg, true));
