@@ -60,7 +60,7 @@ def measured_traffic(kernel: str, n: int, b: int):
         return None
 
 
-def cpu_baseline(n: int = 2816):
+def cpu_baseline(n: int = 3072):
     """The CPU oracle (one-stage Householder + implicit QL, with vectors) on a
     bounded sample of the same workload: one n x n matrix of the same recipe."""
     import numpy as np
