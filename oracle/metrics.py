@@ -11,6 +11,10 @@ epsilon eps = 2^-52 (the convention of LAPACK's test ratios):
     rho_res  = ||A Q - Q diag(w)||_F / (n ||A||_F eps)
     rho_orth = ||Q^T Q - I||_F / (n eps)
     eta      = max_i |w_i - w_ref_i| / ||A||_2,  ||A||_2 = max(|w_ref_1|, |w_ref_n|)
+
+The mixed-precision path is accepted on the same two ratios without the eps
+(the paper's normalisation of Section 3.3.1): ``scaled_residual`` and
+``scaled_orthogonality`` must be <= 1e-13.
 """
 from __future__ import annotations
 
@@ -44,6 +48,16 @@ def backward_error(A, w, Q) -> float:
     n = A.shape[0]
     E = A - (Q * np.asarray(w)[None, :]) @ Q.T
     return float(np.linalg.norm(E) / (n * max(np.linalg.norm(A), 1e-300)))
+
+
+def scaled_residual(A, w, Q) -> float:
+    """||A Q - Q diag(w)||_F / (n ||A||_F) (no eps; A full symmetric)."""
+    return residual(A, w, Q) * EPS
+
+
+def scaled_orthogonality(Q) -> float:
+    """||Q^T Q - I||_F / n (no eps)."""
+    return orthogonality(Q) * EPS
 
 
 def orthogonality(Q) -> float:
