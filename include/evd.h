@@ -8,9 +8,11 @@
  * Method (paper, Sections 2.1 and 3.3): successive band reduction (SBR) of A
  * to a band matrix B of half-bandwidth b with blocked Householder panels and
  * the two-sided ZY update of Eq. 1; bulge chasing (BC) of B to a tridiagonal
- * T; divide and conquer (D&C) on T; back transformation in the reordered
- * stage order of Section 3.3 (SBR-back and BC-back applied to the identity,
- * then one extra GEMM Q = Q_sb * Q_d).
+ * T; divide and conquer (D&C) on T; back transformation, by default in the
+ * conventional order Q = Q_s (H_1 ... H_m Q_d) (BC-back on the D&C vectors,
+ * then SBR-back from the left), or in the reordered order of Section 3.3
+ * (SBR-back and BC-back applied to the identity, then one extra GEMM
+ * Q = Q_sb * Q_d; "order" = 0).
  *
  * Conventions for every entry point:
  *  - Matrices are column-major; element (i, j) of M with leading dimension
@@ -43,8 +45,8 @@ typedef enum {
     EVD_ERR_INVALID_ARG = 1,   /* see evd_last_invalid_arg()                  */
     EVD_ERR_WORKSPACE = 2,     /* work buffer smaller than the queried size   */
     EVD_ERR_HIP = 3,           /* a HIP runtime call failed                   */
-    EVD_ERR_NONFINITE = 4,     /* reserved: non-finite input                  */
-    EVD_ERR_NOT_CONVERGED = 5, /* reserved: host-visible non-convergence      */
+    EVD_ERR_NONFINITE = 4,     /* non-finite input (reported in device info)  */
+    EVD_ERR_NOT_CONVERGED = 5, /* non-convergence (reported in device info)   */
     EVD_ERR_NOT_IMPLEMENTED = 6
 } evd_status_t;
 
@@ -64,7 +66,11 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
 /* Tunables ([host] key strings):
  *   "b"            band half-width of SBR/BC, 0 = automatic (power of two, 4..64)
  *   "bc_waves"     number of persistent bulge-chasing wavefronts, 0 = automatic
- *   "order"        0 = reordered stages (paper Section 3.3), 1 = conventional order
+ *   "order"        1 (default) = conventional stage order Q = Q_s (H_1 ... H_m Q_d),
+ *                  2n^3 + 2n^3 back-transformation flops; 0 = the reordered
+ *                  stages of Section 3.3 (Q_s H_1 ... H_m formed on the
+ *                  identity, then Q = Q_sb Q_d: 4n^3/3 flops more, but
+ *                  independent of D&C until the last product)
  *   "timing"       1 = record per-stage times (host-synchronising; for benchmarks)
  *   "panel_wgs"    0 (default) = each panel-QR workgroup holds as many rows
  *                  as its registers take (512 at b = 64), the fewest
@@ -86,6 +92,9 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "capture_error"  HIP error that made the last batched graph capture fall
  *                  back to a direct run (read only)
  *   "batch_streams", "batch_graph", "last_graph_used"  see evd_dsyevd_batched
+ *   "dc_max_iter"  iterations allowed per secular-equation root in D&C
+ *                  (0 = 200); a small value forces the EVD_ERR_NOT_CONVERGED
+ *                  status in `info` (for tests of the failure path)
  * Unknown keys return EVD_ERR_INVALID_ARG. */
 evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value);
 evd_status_t evd_get_param(evd_ctx_t ctx, const char *key, int64_t *value /*[host]*/);
@@ -134,8 +143,13 @@ evd_status_t evd_sgemm_x3_work_size(evd_ctx_t ctx, int64_t m, int64_t n, int64_t
  *   jobz 'V': eigenvalues -> W and orthonormal eigenvectors -> A (column i
  *             pairs with W[i]).
  *   uplo 'L' or 'U': the triangle of A that is read.
- *   A: n x n, lda >= max(1, n).  W: n doubles.  info: one device int32,
- *   0 on success, > 0 if the tridiagonal solver did not converge.
+ *   A: n x n, lda >= max(1, n).  W: n doubles.
+ *   info: one device int32 holding an evd_status_t: 0 on success,
+ *     EVD_ERR_NONFINITE if the referenced triangle of A holds a NaN or an
+ *       infinity (W, and A for jobz 'V', are then set to NaN),
+ *     EVD_ERR_NOT_CONVERGED if a secular equation of D&C did not converge.
+ *   The input scan and the status stay on the stream (no host round trip):
+ *   the host return value reports only argument and runtime errors.
  *   work: at least evd_dsyevd_work_size() bytes, 256-byte aligned. */
 evd_status_t evd_dsyevd_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n, int64_t lda,
                                   size_t *bytes /*[host]*/);
@@ -241,7 +255,8 @@ evd_status_t evd_dsb2st(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *
  * divide and conquer of Cuppen / Gu-Eisenstat, Tisseur-Dongarra):
  *   compz 'I': W (ascending) and eigenvectors of T in Z (n x n, ldz >= n).
  *   compz 'N': eigenvalues only (Sturm bisection); Z is not referenced.
- * d, e are not modified.  info: device int32, > 0 on non-convergence. */
+ * d, e are not modified.  info: device int32, 0 on success,
+ * EVD_ERR_NOT_CONVERGED if a secular equation did not converge (compz 'I'). */
 evd_status_t evd_dstedc_work_size(evd_ctx_t ctx, char compz, int64_t n, size_t *bytes /*[host]*/);
 evd_status_t evd_dstedc(evd_ctx_t ctx, char compz, int64_t n, const double *d, const double *e,
                         double *W, double *Z, int64_t ldz, void *work, size_t work_bytes, int32_t *info);

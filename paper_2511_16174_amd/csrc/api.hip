@@ -29,6 +29,7 @@ evd_status_t evd_create(evd_ctx_t *ctx, int device)
         if (!c) return EVD_ERR_HIP;
         memset(c, 0, sizeof(*c));
         c->device = -1;
+        c->order = 1;
         *ctx = c;
         return EVD_OK;
     }
@@ -40,6 +41,7 @@ evd_status_t evd_create(evd_ctx_t *ctx, int device)
     c->device = device;
     c->stream = nullptr;
     c->batch_graph = 1;
+    c->order = 1;  // conventional stage order: fewest flops when the stages run one after another
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) { delete c; return EVD_ERR_HIP; }
     if (hipSetDevice(device) != hipSuccess) { delete c; return EVD_ERR_HIP; }
@@ -58,6 +60,13 @@ evd_status_t evd_create(evd_ctx_t *ctx, int device)
 evd_status_t evd_destroy(evd_ctx_t ctx)
 {
     if (!ctx) return EVD_ERR_INVALID_ARG;
+    if (ctx->device >= 0) {
+        // drain the context's own streams before their objects go away
+        (void)hipSetDevice(ctx->device);
+        for (int i = 0; i < ctx->nbstreams; ++i) (void)hipStreamSynchronize(ctx->bstreams[i]);
+        if (ctx->cstream) (void)hipStreamSynchronize(ctx->cstream);
+        if (ctx->astream) (void)hipStreamSynchronize(ctx->astream);
+    }
     for (int i = 0; i < 16; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
@@ -95,6 +104,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "last_graph_used")) return &ctx->last_graph_used;
     if (!strcmp(key, "last_hip_error")) return &ctx->last_hip_error;
     if (!strcmp(key, "capture_error")) return &ctx->capture_error;
+    if (!strcmp(key, "dc_max_iter")) return &ctx->dc_max_iter;
     return nullptr;
 }
 

@@ -179,6 +179,7 @@ struct evd_ctx_s {
     uint64_t gkey;
     int in_batch;             // 1 while the batched driver enqueues its matrices
     hipStream_t astream;      // auxiliary stream: BC-back T factors formed beside D&C
+    int64_t dc_max_iter;      // iterations per secular root (0 = 200; lower values force non-convergence)
 };
 
 // First failing HIP status seen on this host thread (internal helpers without

@@ -316,7 +316,8 @@ __device__ __forceinline__ double group_prod(double v, int L)
 // identical reduced sums, so they take identical decisions).  The root is
 // kept as (origin pole, offset tau) and refined by a bracketed two-pole
 // rational model.
-__global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const double *e, DcArrays a, int L)
+__global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const double *e, DcArrays a, int L,
+                                                       int maxit)
 {
     const int64_t i = blockIdx.y;
     int64_t lo, mid, hi;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(64) void dc_secular_kernel(int64_t n, int t, const 
     double tau = 0.5 * (tlo + thi);
     double last = 1e300;
     bool done = false;
-    for (int it = 0; it < 200; ++it) {
+    for (int it = 0; it < maxit; ++it) {
         double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
         for (int q = sub; q < K; q += L) {
             const double inv = 1.0 / ((D[q] - Do) - tau);
@@ -613,7 +614,7 @@ __global__ void dc_copy_kernel(int64_t n, const double *src, double *dst)
 
 __global__ void dc_info_kernel(const int *flag, int32_t *info)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) info[0] = flag[0];
+    if (threadIdx.x == 0 && blockIdx.x == 0) info[0] = flag[0] ? EVD_ERR_NOT_CONVERGED : 0;
 }
 
 __global__ void dc_zero_int(int *p, int64_t cnt)
@@ -690,6 +691,9 @@ evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const
     }
     DcArrays a;
     dc_layout(n, (char *)work, &a);
+    // iterations per secular root; "dc_max_iter" lowers it to force the
+    // non-convergence status (failure-path tests)
+    const int maxit = (ctx->dc_max_iter > 0 && ctx->dc_max_iter < 200) ? (int)ctx->dc_max_iter : 200;
     hipLaunchKernelGGL(dc_zero_int, dim3(1), dim3(64), 0, s, a.flag, (int64_t)1);
     hipLaunchKernelGGL(dc_init_kernel, grid1(n * n), dim3(256), 0, s, n, d, e, a.Dw, Z, ldz);
     const int levels = (n > 1) ? (int)ceil(log2((double)n)) : 0;
@@ -703,7 +707,7 @@ evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const
         int L = 1;
         while (L < 64 && (int64_t)L * 64 <= smax) L *= 2;
         const unsigned gx = (unsigned)evd_ceil_div(smax, 64 / L);
-        hipLaunchKernelGGL(dc_secular_kernel, dim3(gx, (unsigned)M), dim3(64), 0, s, n, t, e, a, L);
+        hipLaunchKernelGGL(dc_secular_kernel, dim3(gx, (unsigned)M), dim3(64), 0, s, n, t, e, a, L, maxit);
         hipLaunchKernelGGL(dc_zhat_kernel, dim3(gx, (unsigned)M), dim3(64), 0, s, n, t, e, a, L);
         hipLaunchKernelGGL(dc_vec_kernel, dim3((unsigned)smax, (unsigned)M), dim3(64), 0, s, n, t, a);
         EVD_CHECK(gemm_f64_grouped(s, a.probs, (int)(2 * M), smax, smax));

@@ -1,5 +1,5 @@
-// dsyevd-style driver: the two-stage pipeline of the paper in the reordered
-// stage order of Section 3.3.
+// dsyevd-style driver: the two-stage pipeline of the paper, with the back
+// transformation in either stage order of Section 3.3.
 //
 //   SBR (A -> band B, panel reflectors)      stage 1   (Section 2.1.1, Eq. 1)
 //   BC  (B -> T = tridiag(e, d, e), U)       stage 2   (Section 2.1.1)
@@ -7,9 +7,9 @@
 //   SBR-back (Q_s on the identity)           stage 4a  (Section 2.1.2)
 //   BC-back  (Q_sb = Q_s H_1 ... H_m)        stage 4b  (Section 4.3)
 //   final GEMM Q = Q_sb Q_d                  stage 5   (Section 3.3)
-// or, with the "order" parameter set to 1, the conventional order
-// Q = Q_s (H_1 ... H_m Q_d), which needs no final GEMM (fewer flops when the
-// stages run one after the other on one device).
+// That is the reordered order ("order" = 0).  The default ("order" = 1) is
+// the conventional order Q = Q_s (H_1 ... H_m Q_d), which needs no final GEMM
+// (fewer flops when the stages run one after the other on one device).
 // Eigenvalues only: SBR -> BC (no reflectors kept) -> bisection.
 #include "common.h"
 
@@ -31,6 +31,9 @@ evd_status_t bcback_run_rev(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, 
 evd_status_t ormsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *C,
                        int64_t ldc, void *work);
 evd_status_t transpose_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *B, int64_t ldb);
+evd_status_t nonfinite_begin(hipStream_t s, int64_t n, double *A, int64_t lda, char uplo, int *flag);
+evd_status_t nonfinite_end(hipStream_t s, int64_t n, const int *flag, double *W, double *A, int64_t lda, bool vec,
+                           int32_t *info);
 
 namespace {
 
@@ -38,7 +41,7 @@ int64_t choose_b(evd_ctx_t ctx, int64_t n) { return evd_choose_b(ctx, n); }
 
 struct EvdWork {
     double *AB, *T, *d, *e, *V, *TAU, *Qs, *Qd, *Tg;
-    int *prog;
+    int *prog, *nflag;
     void *sbr, *dc, *orgsb;
     int64_t b, ldab;
 };
@@ -62,6 +65,7 @@ size_t evd_layout(int64_t n, int64_t b, bool vec, char *base, EvdWork *w)
     t.d = (double *)take(nn * 8);
     t.e = (double *)take(nn * 8);
     t.prog = (int *)take(nn * 4);
+    t.nflag = (int *)take(256);
     t.sbr = take(sbr_work_bytes(n, b));
     if (vec) {
         t.V = (double *)take((size_t)(steps > 0 ? steps : 1) * nn * b * 8);
@@ -91,11 +95,12 @@ __global__ void copy_kernel(int64_t n, const double *src, int64_t lds, double *d
 __global__ void trivial_kernel(int64_t n, double *A, double *W, int vec, int32_t *info)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const bool finite = n != 1 || isfinite(A[0]);
         if (n == 1) {
             W[0] = A[0];
-            if (vec) A[0] = 1.0;
+            if (vec) A[0] = finite ? 1.0 : __longlong_as_double(0x7ff8000000000000ll);
         }
-        if (info) info[0] = 0;
+        if (info) info[0] = finite ? 0 : EVD_ERR_NONFINITE;
     }
 }
 
@@ -161,6 +166,7 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
     auto mark = [&](int i) { if (timing) (void)hipEventRecord(ctx->ev[i], s); };
 
     mark(0);
+    EVD_CHECK(nonfinite_begin(s, n, A, lda, uplo, w.nflag));
     EVD_CHECK(sbr_run(ctx, uplo, n, b, A, lda, w.AB, w.ldab, w.T, w.sbr));
     mark(1);
     EVD_CHECK(bc_run(ctx, vec ? 'V' : 'N', n, b, w.AB, w.ldab, w.d, w.e, w.V, w.TAU, w.prog));
@@ -220,6 +226,7 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
             mark(6);
         }
     }
+    EVD_CHECK(nonfinite_end(s, n, w.nflag, W, A, lda, vec, info));
     if (timing) {
         if (hipEventSynchronize(ctx->ev[vec ? 6 : 3]) != hipSuccess) return EVD_ERR_HIP;
         float ms = 0.0f;

@@ -24,6 +24,9 @@ size_t orgsb_work_bytes(int64_t n, int64_t b);
 evd_status_t bcback_run_f32(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const float *V, const float *TAU,
                             float *Q, int64_t ldq);
 size_t refine_work_bytes(int64_t n);
+evd_status_t nonfinite_begin(hipStream_t s, int64_t n, double *A, int64_t lda, char uplo, int *flag);
+evd_status_t nonfinite_end(hipStream_t s, int64_t n, const int *flag, double *W, double *A, int64_t lda, bool vec,
+                           int32_t *info);
 evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
                         int sweeps, void *work, double *stats);
 
@@ -92,7 +95,7 @@ int64_t choose_b_mixed(evd_ctx_t ctx, int64_t n) { return evd_choose_b(ctx, n); 
 struct MixWork {
     float *A32, *AB, *T, *V, *TAU, *Qs, *Qd32, *X32;
     double *d, *e, *Qd, *Xd, *lam, *stats;
-    int *prog, *pos;
+    int *prog, *pos, *nflag;
     void *sbr, *dc, *orgsb, *ref;
     int64_t b, ldab;
 };
@@ -125,6 +128,7 @@ size_t mix_layout(int64_t n, int64_t b, char *base, MixWork *w)
     t.stats = (double *)take(64);
     t.prog = (int *)take(nn * 4);
     t.pos = (int *)take(nn * 4);
+    t.nflag = (int *)take(256);
     t.sbr = take(sbr_work_bytes_f32(n, b));
     t.orgsb = take(orgsb_work_bytes(n, b));
     t.Xd = (double *)take(nn * nn * 8);
@@ -195,6 +199,7 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     const int64_t nn = n * n;
 
     mark(0);
+    EVD_CHECK(nonfinite_begin(s, n, A, lda, uplo, w.nflag));
     hipLaunchKernelGGL(mx_down_lower_kernel, g, t, 0, s, n, (const double *)A, lda, w.A32, up ? 1 : 0);
     if (up) hipLaunchKernelGGL(mx_mirror_upper_kernel, g, t, 0, s, n, A, lda);  // refinement reads the lower triangle
     EVD_CHECK(sbr_run_f32(ctx, 'L', n, b, w.A32, n, w.AB, w.ldab, w.T, w.sbr));
@@ -216,6 +221,7 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     hipLaunchKernelGGL(mx_scatter_kernel, g, t, 0, s, n, (const double *)w.Xd, (const double *)w.lam,
                        (const int *)w.pos, A, lda, W);
     if (stats) (void)hipMemcpyAsync(stats, w.stats, 8 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    EVD_CHECK(nonfinite_end(s, n, w.nflag, W, A, lda, true, info));
     mark(7);
     if (timing) {
         if (hipEventSynchronize(ctx->ev[7]) != hipSuccess) return EVD_ERR_HIP;

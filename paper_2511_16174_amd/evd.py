@@ -8,8 +8,10 @@ raises ImportError-like ``RuntimeError`` -- there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libevd.so")
@@ -109,8 +111,17 @@ def _ch(c: str) -> bytes:
     return c.encode()[:1]
 
 
+_live_contexts = weakref.WeakSet()
+
+
 class Context:
-    """Owns one ``evd_ctx_t``.  The stream defaults to torch's current stream."""
+    """Owns one ``evd_ctx_t``.  The stream defaults to torch's current stream.
+
+    Every live context is closed by an ``atexit`` hook, i.e. while the HIP
+    runtime (and any profiler attached to it) is still up: a context owns
+    streams, events and possibly an instantiated graph, and destroying those
+    from a finaliser during interpreter teardown would call into a runtime
+    that is already being torn down."""
 
     def __init__(self, device: int = 0):
         self.lib = load_library()
@@ -120,6 +131,7 @@ class Context:
             raise EvdError("evd_create", st)
         self.handle = h
         self.device = device
+        _live_contexts.add(self)
 
     def close(self):
         if self.handle:
@@ -301,7 +313,26 @@ def evd_bc_num_steps(n: int, b: int) -> int:
     return int(load_library().evd_bc_num_steps(n, b))
 
 
+def raise_for_info(func: str, info: int):
+    """Raise EvdError for a nonzero device status word (an evd_status_t:
+    EVD_ERR_NONFINITE or EVD_ERR_NOT_CONVERGED)."""
+    if info != 0:
+        status = info if info in (EVD_ERR_NONFINITE, EVD_ERR_NOT_CONVERGED) else EVD_ERR_NOT_CONVERGED
+        raise EvdError(func, status, info)
+
+
 _default_ctx = {}
+
+
+@atexit.register
+def close_all():
+    """Destroy every live context (registered with ``atexit``)."""
+    _default_ctx.clear()
+    for ctx in list(_live_contexts):
+        try:
+            ctx.close()
+        except Exception:
+            pass
 
 
 def context(device: int = 0) -> Context:
@@ -325,8 +356,7 @@ def eigh_mixed(A, sweeps: int = 2, uplo: str = "L", b: int = 0, ctx: Context | N
     wb = ctx.evd_dsyevd_mixed_work_size("V", uplo, n, max(n, 1))
     work = torch.empty(max(wb, 256) // 8 + 32, dtype=torch.float64, device=A.device)
     ctx.evd_dsyevd_mixed("V", uplo, n, Acm, max(n, 1), W, sweeps, work, wb, info, stats)
-    if int(info.item()) != 0:
-        raise EvdError("evd_dsyevd_mixed", EVD_ERR_NOT_CONVERGED, int(info.item()))
+    raise_for_info("evd_dsyevd_mixed", int(info.item()))
     return W[:n], Acm, stats
 
 
@@ -352,8 +382,7 @@ def eigh(A, jobz: str = "V", uplo: str = "L", b: int = 0, ctx: Context | None = 
     wb = ctx.evd_dsyevd_work_size(jobz, uplo, n, max(n, 1))
     work = torch.empty(max(wb, 256) // 8 + 32, dtype=torch.float64, device=A.device)
     ctx.evd_dsyevd(jobz, uplo, n, Acm, max(n, 1), W, work, wb, info)
-    if int(info.item()) != 0:
-        raise EvdError("evd_dsyevd", EVD_ERR_NOT_CONVERGED, int(info.item()))
+    raise_for_info("evd_dsyevd", int(info.item()))
     w = W[:n]
     if jobz.upper() == "V":
         return w, Acm

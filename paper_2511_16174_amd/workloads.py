@@ -128,6 +128,36 @@ def known_spectrum(n: int, seed: int, spectrum: str = "clustered", reflectors: i
     return A, lam
 
 
+def known_spectrum_device(n: int, seed: int, spectrum: str = "clustered", reflectors: int = 64,
+                          device="cuda"):
+    """:func:`known_spectrum` assembled on a GPU: the same PCG64 draws in the
+    same order on the host, then the two-sided reflector updates with torch
+    FP64 tensor operations on ``device`` (the host assembly takes minutes at
+    n = 8192 and beyond).  Returns (A as a torch tensor, lam_sorted numpy)."""
+    import torch
+
+    r = rng(seed)
+    V = reflector_vectors(n, reflectors, r)
+    if spectrum == "clustered":
+        lam = clustered_spectrum(n, r)
+    elif spectrum == "logspaced":
+        lam = logspaced_spectrum(n, r)
+    elif spectrum == "uniform":
+        lam = np.sort(r.uniform(-1.0, 1.0, size=n))
+    else:
+        lam = table2_spectrum(spectrum, n, r)
+    A = torch.diag(torch.from_numpy(lam).to(device))
+    for v in V[::-1]:
+        v = torch.from_numpy(v / np.linalg.norm(v)).to(device)
+        Av = A @ v
+        vAv = float(v @ Av)
+        A -= 2.0 * torch.outer(v, Av)
+        A -= 2.0 * torch.outer(Av, v)
+        A += 4.0 * vAv * torch.outer(v, v)
+    A = 0.5 * (A + A.t())
+    return A.contiguous(), lam
+
+
 def laplacian_1d(n: int) -> np.ndarray:
     """tridiag(-1, 2, -1); eigenvalues 2 - 2 cos(k pi/(n+1)), k = 1..n."""
     A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)

@@ -40,3 +40,37 @@ def band_to_dense(AB, n, b, ldab):
             B[j + d, j] = AB[d, j]
             B[j, j + d] = AB[d, j]
     return B
+
+
+class params:
+    """Set context parameters for a block and restore the previous values."""
+
+    def __init__(self, ctx, **kv):
+        self.ctx, self.kv, self.saved = ctx, kv, {}
+
+    def __enter__(self):
+        for k, v in self.kv.items():
+            self.saved[k] = self.ctx.get_param(k)
+            self.ctx.set_param(k, v)
+        return self.ctx
+
+    def __exit__(self, *exc):
+        for k, v in self.saved.items():
+            self.ctx.set_param(k, v)
+        return False
+
+
+def device_ratios(A0, w, X, eps=2.0 ** -52):
+    """rho_res, rho_orth of the eigenpairs (w, X) of the symmetric A0 (torch
+    FP64 tensors on the GPU, X[:, j] the j-th vector), with torch's own FP64
+    products (independent of the library under test)."""
+    t = torch()
+    n = A0.shape[0]
+    with t.no_grad():
+        R = A0 @ X - X * w[None, :]
+        res = (t.linalg.norm(R) / (n * t.linalg.norm(A0) * eps)).item()
+        del R
+        O = X.t() @ X
+        O.diagonal().sub_(1.0)
+        orth = (t.linalg.norm(O) / (n * eps)).item()
+    return res, orth

@@ -114,3 +114,25 @@ def test_dgemm_valid_args_reach_device_check(vctx):
     lib, h = vctx
     st = lib.evd_dgemm(h, b"N", b"T", 0, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None, 0)
     assert st == evd.EVD_ERR_HIP  # validation passed; no device in this context
+
+
+def test_defaults_and_failure_knobs(vctx):
+    """The conventional stage order is the default; the D&C iteration cap
+    (failure-path knob) is a settable parameter."""
+    lib, h = vctx
+    v = ctypes.c_int64()
+    assert lib.evd_get_param(h, b"order", ctypes.byref(v)) == evd.EVD_OK and v.value == 1
+    assert lib.evd_set_param(h, b"dc_max_iter", 1) == evd.EVD_OK
+    assert lib.evd_get_param(h, b"dc_max_iter", ctypes.byref(v)) == evd.EVD_OK and v.value == 1
+    assert lib.evd_set_param(h, b"dc_max_iter", 0) == evd.EVD_OK
+    assert lib.evd_status_string(evd.EVD_ERR_NONFINITE) == b"non-finite input"
+    assert lib.evd_status_string(evd.EVD_ERR_NOT_CONVERGED) == b"not converged"
+
+
+def test_device_status_word_maps_to_errors():
+    evd.raise_for_info("f", 0)
+    for info, status in ((evd.EVD_ERR_NONFINITE, evd.EVD_ERR_NONFINITE),
+                         (evd.EVD_ERR_NOT_CONVERGED, evd.EVD_ERR_NOT_CONVERGED), (1, evd.EVD_ERR_NOT_CONVERGED)):
+        with pytest.raises(evd.EvdError) as e:
+            evd.raise_for_info("f", info)
+        assert e.value.status == status and e.value.arg == info

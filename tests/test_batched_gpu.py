@@ -109,3 +109,51 @@ def test_autotune_picks_a_candidate_and_keeps_parity():
     w, Q = w.cpu().numpy(), Q.cpu().numpy()
     assert M.eig_error(w, oracle.syev(A, jobz="N")) <= 1e-12
     assert M.residual(A, w, Q) <= 10 and M.orthogonality(Q) <= 10
+
+
+def test_batched_nonfinite_matrix_sets_only_its_own_status():
+    """One matrix of the batch holds a NaN: its info entry reports
+    EVD_ERR_NONFINITE and NaN outputs; every other matrix is solved."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    Ls, mats = make_batch(6, seed=13, lmin=4, lmax=10)
+    bad = 3
+    mats[bad] = mats[bad].copy()
+    mats[bad][2, 2] = np.nan
+    ws, Qs, info, _, used = run_batched(ctx, mats, graph=1, reps=1)[0]
+    assert info[bad] == evd.EVD_ERR_NONFINITE
+    assert np.all(np.isnan(ws[bad])) and np.all(np.isnan(Qs[bad]))
+    for i, (A, w, Q) in enumerate(zip(mats, ws, Qs)):
+        if i == bad:
+            continue
+        assert info[i] == 0
+        assert M.eig_error(w, oracle.syev(A, jobz="N")) <= 1e-12
+        assert M.residual(A, w, Q) <= 10 and M.orthogonality(Q) <= 10
+
+
+def test_batched_bj_c5_full_batch():
+    """The batched workload at its real size: 256 tight-binding Hamiltonians,
+    L ~ U{8..45} (n = 64..2025), on-site energies U[-2, 2], seed 7, with
+    vectors, in one captured graph.  rho_res and rho_orth of every matrix
+    (torch FP64 products on the GPU); eigenvalues of 8 matrices spread over
+    the size range against the CPU oracle; device timestamps ordered."""
+    import torch
+    from paper_2511_16174_amd import evd
+    from tests.gpu_helpers import device_ratios
+    ctx = evd.context(0)
+    Ls, mats = make_batch(256, seed=7, lmin=8, lmax=45)
+    ws, Qs, info, stamps, used = run_batched(ctx, mats, graph=1, reps=1)[0]
+    assert np.all(info == 0)
+    worst_res = worst_orth = 0.0
+    for A, w, Q in zip(mats, ws, Qs):
+        assert np.all(np.diff(w) >= 0)
+        res, orth = device_ratios(torch.from_numpy(A).cuda(), torch.from_numpy(w).cuda(),
+                                  torch.from_numpy(np.ascontiguousarray(Q)).cuda())
+        worst_res, worst_orth = max(worst_res, res), max(worst_orth, orth)
+    print(f"BJ.c5: worst rho_res={worst_res:.3f} worst rho_orth={worst_orth:.3f} graph={used}")
+    assert worst_res <= 10 and worst_orth <= 10
+    order = np.argsort([m.shape[0] for m in mats])
+    for i in order[np.linspace(0, len(mats) - 1, 8).astype(int)]:
+        assert M.eig_error(ws[i], oracle.syev(mats[i], jobz="N")) <= 1e-12, (i, mats[i].shape[0])
+    st = stamps.reshape(-1, 2)
+    assert np.all(st[:, 1] >= st[:, 0]) and np.all(st[:, 0] > 0)
