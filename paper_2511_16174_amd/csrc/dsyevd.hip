@@ -96,9 +96,10 @@ __global__ void trivial_kernel(int64_t n, double *A, double *W, int vec, int32_t
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const bool finite = n != 1 || isfinite(A[0]);
+        const double nan = __longlong_as_double(0x7ff8000000000000ll);
         if (n == 1) {
-            W[0] = A[0];
-            if (vec) A[0] = finite ? 1.0 : __longlong_as_double(0x7ff8000000000000ll);
+            W[0] = finite ? A[0] : nan;
+            if (vec) A[0] = finite ? 1.0 : nan;
         }
         if (info) info[0] = finite ? 0 : EVD_ERR_NONFINITE;
     }
