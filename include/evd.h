@@ -156,6 +156,23 @@ evd_status_t evd_dsyevd_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n
 evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda,
                         double *W, void *work, size_t work_bytes, int32_t *info);
 
+/* evd_dsyevd without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, outputs, `info` and host status
+ * as evd_dsyevd; the scratch is a static device array of
+ * EVD_NOALLOC_SCRATCH_BYTES per GPU, held by the library on every GPU it
+ * runs on until the process ends, whose address is looked up by evd_create.
+ * The call itself allocates nothing (no device allocation, no stream or event
+ * creation).  Returns EVD_ERR_WORKSPACE (evd_last_invalid_arg = 4) when
+ * evd_dsyevd_work_size(jobz, uplo, n, lda) exceeds that size: at the default
+ * band width n <= 1151 fits with vectors, n <= 5262 for eigenvalues only.
+ * All calls on one GPU share its array: calls that overlap on one GPU (two
+ * streams, two host threads, two contexts) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe. */
+#define EVD_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+evd_status_t evd_dsyevd_noalloc(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda,
+                                double *W, int32_t *info);
+
 /* Mixed-precision EVD with FP64 refinement (an extension beside the paper's
  * FP64 path; not in the paper).  The pipeline of evd_dsyevd runs in FP32
  * (panel QR, bulge chasing and BC-back on FP32 vector units; every product

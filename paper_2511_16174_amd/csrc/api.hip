@@ -50,8 +50,17 @@ evd_status_t evd_create(evd_ctx_t *ctx, int device)
     c->num_cus = prop.multiProcessorCount;
     gemm_set_cu_count(c->num_cus);
     for (int i = 0; i < 16; ++i) {
-        if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete c; return EVD_ERR_HIP; }
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) { evd_destroy(c); return EVD_ERR_HIP; }
     }
+    // auxiliary stream (default priority) for work formed beside D&C; created
+    // here so that no compute call creates runtime objects
+    if (hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking) != hipSuccess) {
+        c->astream = nullptr;
+        evd_destroy(c);
+        return EVD_ERR_HIP;
+    }
+    // device address of the allocation-free entry point's static scratch
+    if (noalloc_init_device(device) != EVD_OK) { evd_destroy(c); return EVD_ERR_HIP; }
     (void)hipSetDevice(prev);
     *ctx = c;
     return EVD_OK;

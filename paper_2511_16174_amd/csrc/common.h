@@ -222,6 +222,8 @@ inline int64_t evd_choose_b(const evd_ctx_s *ctx, int64_t n)
 }
 
 // ---------------------------------------------------------------- internal API
+// device address of the allocation-free entry point's scratch (noalloc.hip)
+evd_status_t noalloc_init_device(int device);
 // GEMM (gemm_f64.hip)
 enum { OP_N = 0, OP_T = 1, OP_S = 2 };
 evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, int64_t n, int64_t k,

@@ -180,9 +180,8 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
         // so they are formed on an auxiliary stream while D&C runs (not in
         // the batched driver, whose streams are captured into a graph)
         const bool blocked_c = ctx->order != 0 && w.Tg && ctx->bcback_valu == 0 && bcback_mfma_fits(n);
-        const bool ahead = blocked_c && !ctx->in_batch;
+        const bool ahead = blocked_c && !ctx->in_batch && ctx->astream;
         if (ahead) {
-            if (!ctx->astream) EVD_CHECK(evd_hip(ctx, hipStreamCreateWithFlags(&ctx->astream, hipStreamNonBlocking)));
             EVD_CHECK(evd_hip(ctx, hipEventRecord(ctx->ev[8], s)));
             EVD_CHECK(evd_hip(ctx, hipStreamWaitEvent(ctx->astream, ctx->ev[8], 0)));
             ctx->stream = ctx->astream;

@@ -45,6 +45,7 @@ PROTOTYPES = {
     "evd_sgemm_x3_work_size": (_st, [_vp, _i64, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dsyevd_work_size": (_st, [_vp, _c, _c, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dsyevd": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "evd_dsyevd_noalloc": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _vp]),
     "evd_dsyevd_mixed_work_size": (_st, [_vp, _c, _c, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dsyevd_mixed": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _i32, _vp, _sz, _vp, _vp]),
     "evd_autotune_work_size": (_st, [_vp, _c, _i64, ctypes.POINTER(_sz)]),
@@ -204,6 +205,11 @@ class Context:
         st = self.lib.evd_dsyevd(self.handle, _ch(jobz), _ch(uplo), n, _ptr(A), lda, _ptr(W), _ptr(work),
                                  work_bytes, _ptr(info))
         self._check("evd_dsyevd", st)
+
+    def evd_dsyevd_noalloc(self, jobz, uplo, n, A, lda, W, info):
+        self.set_stream()
+        st = self.lib.evd_dsyevd_noalloc(self.handle, _ch(jobz), _ch(uplo), n, _ptr(A), lda, _ptr(W), _ptr(info))
+        self._check("evd_dsyevd_noalloc", st)
 
     def evd_dsyevd_mixed_work_size(self, jobz, uplo, n, lda) -> int:
         b = _sz()
