@@ -177,22 +177,32 @@ evd_status_t evd_dsyevd_noalloc(evd_ctx_t ctx, char jobz, char uplo, int64_t n, 
  * FP64 path; not in the paper).  The pipeline of evd_dsyevd runs in FP32
  * (panel QR, bulge chasing and BC-back on FP32 vector units; every product
  * through split-BF16x3 matrix cores, see evd_sgemm_x3), the tridiagonal
- * eigenproblem in FP64, then `sweeps` FP64 Ogita-Aishima refinement sweeps
+ * eigenproblem in FP64, then FP64 Ogita-Aishima refinement sweeps
  * (R = I - X^T X, S = X^T A X, lam_i = s_ii/(1 - r_ii),
  * E_ij = (s_ij + lam_j r_ij)/(lam_j - lam_i) if |lam_i - lam_j| > delta else
- * r_ij/2, X <- X + X E) improve the eigenpairs.  Outputs as evd_dsyevd
- * (jobz must be 'V'; W ascending, eigenvectors in A; W holds the Rayleigh
- * quotients of the returned vectors).  0 <= sweeps <= 8.
- * stats (optional, device, 8 doubles): [0] delta of the last sweep,
- * [1] ||S - diag(lam)||_F, [2] ||R||_F, [3] max |lam|, [4] the FP64 residual
- * ||A X - X diag(W)||_F / (n ||A||_F) of the returned pairs.
+ * r_ij/2, X <- X + X E; eigenvalues closer than delta are resolved by a
+ * Rayleigh-Ritz step inside the sweep) improve the eigenpairs.  Outputs as
+ * evd_dsyevd (jobz must be 'V'; W ascending, eigenvectors in A; W holds the
+ * Rayleigh quotients of the returned vectors).
+ *   max_sweeps: 0..8 refinement sweeps at most.
+ *   target_residual > 0: the sweeps stop as soon as the scaled residual
+ *     ||A X - X diag(W)||_F / (n ||A||_F) and the orthogonality
+ *     ||X^T X - I||_F / n are both <= target_residual (the call then
+ *     synchronises with its stream once per sweep); if they are not reached
+ *     after max_sweeps, info = EVD_ERR_NOT_CONVERGED (the pairs are still
+ *     returned).  target_residual <= 0: exactly max_sweeps sweeps, no status.
+ *   achieved (optional, device, 8 doubles): [0] the achieved scaled residual,
+ *     [1] the orthogonality above, [2] sweeps run, and of the last sweep
+ *     [3] delta, [4] clusters resolved by Rayleigh-Ritz, [5] the largest
+ *     cluster size, [6] ||S - diag(lam)||_F, [7] ||R||_F.  Not written for
+ *     n < 3 (solved by the FP64 driver).
  * Stage times ("timing" = 1): [0] SBR, [1] BC, [2] D&C, [3] SBR-back,
  * [4] BC-back, [5] final product, [6] refinement, [7] total. */
 evd_status_t evd_dsyevd_mixed_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n, int64_t lda,
                                         size_t *bytes /*[host]*/);
 evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda,
-                              double *W, int32_t sweeps, void *work, size_t work_bytes, int32_t *info,
-                              double *stats);
+                              double *W, int32_t max_sweeps, double target_residual, void *work,
+                              size_t work_bytes, int32_t *info, double *achieved);
 
 /* Autotuner for the band half-width b (the paper fixes b = 32 for its
  * platform, Section 4.1; the best b depends on the GPU and on n).  Times

@@ -28,7 +28,7 @@ evd_status_t nonfinite_begin(hipStream_t s, int64_t n, double *A, int64_t lda, c
 evd_status_t nonfinite_end(hipStream_t s, int64_t n, const int *flag, double *W, double *A, int64_t lda, bool vec,
                            int32_t *info);
 evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
-                        int sweeps, void *work, double *stats);
+                        int max_sweeps, double target, void *work, double *stats, int *done);
 
 namespace {
 
@@ -88,6 +88,15 @@ __global__ void mx_scatter_kernel(int64_t n, const double *X, const double *lam,
         A[i + pj * lda] = X[idx];
         if (i == 0) W[pj] = lam[j];
     }
+}
+
+// info = EVD_ERR_NOT_CONVERGED when a target was given and the returned pairs
+// miss it (residual or orthogonality); an earlier status is kept
+__global__ void mx_target_kernel(const double *stats, double target, int32_t *info)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && info && target > 0.0 && info[0] == 0 &&
+        !(stats[0] <= target && stats[1] <= target))
+        info[0] = EVD_ERR_NOT_CONVERGED;
 }
 
 int64_t choose_b_mixed(evd_ctx_t ctx, int64_t n) { return evd_choose_b(ctx, n); }
@@ -163,7 +172,8 @@ evd_status_t evd_dsyevd_mixed_work_size(evd_ctx_t ctx, char jobz, char uplo, int
 }
 
 evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda, double *W,
-                              int32_t sweeps, void *work, size_t work_bytes, int32_t *info, double *stats)
+                              int32_t max_sweeps, double target_residual, void *work, size_t work_bytes,
+                              int32_t *info, double *achieved)
 {
     if (!ctx) return EVD_ERR_INVALID_ARG;
     const int64_t b = choose_b_mixed(ctx, n);
@@ -174,11 +184,12 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     else if (n > 0 && !A) bad = 5;
     else if (lda < (n > 1 ? n : 1)) bad = 6;
     else if (n > 0 && !W) bad = 7;
-    else if (sweeps < 0 || sweeps > 8) bad = 8;
-    else if (n > 0 && !work) bad = 9;
-    else if (work_bytes < mix_layout(n, b, nullptr, nullptr)) bad = 10;
+    else if (max_sweeps < 0 || max_sweeps > 8) bad = 8;
+    else if (!(target_residual == target_residual)) bad = 9;
+    else if (n > 0 && !work) bad = 10;
+    else if (work_bytes < mix_layout(n, b, nullptr, nullptr)) bad = 11;
     ctx->last_invalid_arg = bad;
-    if (bad) return bad == 10 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
+    if (bad) return bad == 11 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
     EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
@@ -216,11 +227,14 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     EVD_CHECK(gemm_f32x3(s, OP_N, OP_N, 0, n, n, n, 1.0f, w.Qs, n, w.Qd32, n, 0.0f, w.X32, n, nullptr, 0));
     hipLaunchKernelGGL(mx_up_kernel, g, t, 0, s, nn, (const float *)w.X32, w.Xd);
     mark(6);
-    EVD_CHECK(refine_run(ctx, n, A, lda, w.Xd, n, w.lam, sweeps, w.ref, w.stats));
+    int done = 0;
+    EVD_CHECK(refine_run(ctx, n, A, lda, w.Xd, n, w.lam, max_sweeps, target_residual, w.ref, w.stats, &done));
+    hipLaunchKernelGGL(mx_target_kernel, dim3(1), dim3(64), 0, s, (const double *)w.stats, target_residual, info);
     hipLaunchKernelGGL(mx_rank_kernel, dim3((unsigned)evd_ceil_div(n, 256)), t, 0, s, n, (const double *)w.lam, w.pos);
     hipLaunchKernelGGL(mx_scatter_kernel, g, t, 0, s, n, (const double *)w.Xd, (const double *)w.lam,
                        (const int *)w.pos, A, lda, W);
-    if (stats) (void)hipMemcpyAsync(stats, w.stats, 8 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (achieved) EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(achieved, w.stats, 8 * sizeof(double),
+                                                         hipMemcpyDeviceToDevice, s)));
     EVD_CHECK(nonfinite_end(s, n, w.nflag, W, A, lda, true, info));
     mark(7);
     if (timing) {

@@ -243,13 +243,27 @@ __global__ __launch_bounds__(256) void oa_rr_kernel(int64_t n, const double *S, 
             }
         }
     }
+    // Ritz values ascending (ties by index): column c of N V goes to position
+    // rank(c), so the cluster's columns stay in eigenvalue order for the
+    // next sweep's consecutive-gap clustering
+    __shared__ int rank_[OA_KMAX];
+    for (int c = tid; c < k; c += 256) {
+        const double key = A0[c * LD + c];
+        int r = 0;
+        for (int q = 0; q < k; ++q) {
+            const double v = A0[q * LD + q];
+            r += (v < key || (v == key && q < c)) ? 1 : 0;
+        }
+        rank_[c] = r;
+    }
+    __syncthreads();
     for (int e = tid; e < k * k; e += 256) {
         const int a = e % k, c = e / k;
         double t = 0.0;
         for (int p = 0; p < k; ++p) t += A1[a * LD + p] * A2[p * LD + c];
-        Wg[off + e] = t;
+        Wg[off + a + rank_[c] * k] = t;
     }
-    for (int a = tid; a < k; a += 256) lam[b0 + a] = A0[a * LD + a];
+    for (int a = tid; a < k; a += 256) lam[b0 + rank_[a]] = A0[a * LD + a];
     }
 }
 
@@ -430,11 +444,51 @@ __global__ __launch_bounds__(64) void oa_rayleigh_kernel(int64_t n, const double
     if (threadIdx.x == 0) lam[j] = num / den;
 }
 
-__global__ void oa_meta_stats_kernel(const int *meta, double *stats)
+// M(j, i) <- M(i, j) for i > j: the products whose lower triangle alone is
+// computed (R = I - X^T X and S = X^T (A X), symmetric) in full storage
+__global__ void oa_mirror_kernel(int64_t n, double *M)
+{
+    const int64_t total = n * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % n, j = idx / n;
+        if (i > j) M[j + i * n] = M[idx];
+    }
+}
+
+// ||R||_F^2 partials (R = I - X^T X in full storage)
+__global__ __launch_bounds__(256) void oa_rnorm_kernel(int64_t n, const double *R, double *part)
+{
+    __shared__ double r0[4];
+    double a = 0.0;
+    const int64_t total = n * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x)
+        a += R[idx] * R[idx];
+    a = wave_sum(a);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) r0[w] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = r0[0] + r0[1] + r0[2] + r0[3];
+}
+
+__global__ void oa_orth_final_kernel(int nblk, int64_t n, const double *part, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0;
+    for (int q = 0; q < nblk; ++q) a += part[q];
+    out[0] = sqrt(a) / (double)n;
+}
+
+// last sweep's figures into the caller's statistics: [2] sweeps, [3] delta,
+// [4] clusters resolved, [5] largest cluster, [6] ||S - diag(lam)||_F, [7] ||R||_F
+__global__ void oa_meta_stats_kernel(const int *meta, const double *dl, int sweeps, double *stats)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        stats[5] = (double)meta[0];
-        stats[6] = (double)meta[1];
+        stats[2] = (double)sweeps;
+        stats[3] = sweeps > 0 ? dl[0] : 0.0;
+        stats[4] = sweeps > 0 ? (double)meta[0] : 0.0;
+        stats[5] = sweeps > 0 ? (double)meta[1] : 0.0;
+        stats[6] = sweeps > 0 ? dl[1] : 0.0;
+        stats[7] = sweeps > 0 ? dl[2] : 0.0;
     }
 }
 
@@ -447,14 +501,14 @@ size_t dsyevd_work_bytes_any_b(int64_t n);
 namespace {
 
 // Large clusters (more than OA_KMAX members) are resolved with the FP64
-// two-stage solver on their k x k block; their blocks share one store of
-// OA_BIG_FRAC^2 n^2 doubles (clusters that no longer fit stay unresolved).
-constexpr double OA_BIG_FRAC = 0.75;
-
-int64_t big_capacity(int64_t n) { return n > OA_KMAX ? (int64_t)(OA_BIG_FRAC * (double)n) : 0; }
+// two-stage solver on their k x k block; their rotations share one store of
+// n^2 doubles (the clusters are disjoint, so every cluster fits: a cluster
+// left unresolved would get Newton updates between members whose gaps only
+// just exceed delta, and lose orthogonality).
+int64_t big_capacity(int64_t n) { return n > OA_KMAX ? n : 0; }
 
 struct RefWork {
-    double *R, *AX, *S, *Xn, *part, *Wg;
+    double *R, *AX, *S, *Xn, *part, *Wg, *dl;
     int *cid, *cl, *meta, *big;
     double *bN, *bM, *bW, *bmu;
     void *bws;
@@ -478,6 +532,7 @@ size_t ref_layout(int64_t n, char *base, RefWork *w)
     t.Xn = (double *)take(nn * nn * 8);
     t.part = (double *)take((size_t)OA_BLOCKS * 3 * 8);
     t.Wg = (double *)take(nn * OA_KMAX * 8);
+    t.dl = (double *)take(64);
     t.cid = (int *)take(nn * 4);
     t.cl = (int *)take(nn * 3 * 4);
     t.meta = (int *)take(64);
@@ -571,15 +626,22 @@ evd_status_t big_clusters_end(evd_ctx_t ctx, int64_t n, double *E, RefWork &w, c
 
 size_t refine_work_bytes(int64_t n) { return ref_layout(n, nullptr, nullptr); }
 
-// One or more RefSyEv sweeps on X (n x n, ldx), A lower-stored FP64, on the
-// context's stream.  lam (n) receives the refined eigenvalue estimates.
-// stats (device, 8 doubles): [0] delta, [1] ||S - diag(lam)||_F, [2] ||R||_F,
-// [3] max|lam| of the last sweep, [4] residual ||A X - X lam||_F / (n ||A||_F)
-// of the final X, whose Rayleigh quotients are returned in lam, [5] clusters
-// resolved by Rayleigh-Ritz and [6] the largest cluster size in the last sweep.
-// Large clusters make the call synchronise with the stream once per sweep.
+// RefSyEv sweeps on X (n x n, ldx), A lower-stored FP64, on the context's
+// stream, at most max_sweeps of them.  Before each sweep (and after the
+// last) the current X is checked: R = I - X^T X and A X are formed (they are
+// the sweep's first products anyway), lam = the Rayleigh quotients of X's
+// columns, stats[0] = ||A X - X diag(lam)||_F / (n ||A||_F) and stats[1] =
+// ||X^T X - I||_F / n.  With target > 0 the check is read on the host (one
+// synchronisation per sweep) and the sweeps stop once both are <= target;
+// with target <= 0 exactly max_sweeps sweeps run without a host round trip
+// (resolving clusters of more than 64 members reads the cluster list back,
+// once per sweep).  stats (device, 8 doubles): [0] residual and [1]
+// orthogonality of the returned X, [2] sweeps run, then of the last sweep
+// [3] delta, [4] clusters resolved by Rayleigh-Ritz, [5] the largest cluster
+// size, [6] ||S - diag(lam)||_F, [7] ||R||_F.  lam (n) receives the Rayleigh
+// quotients of the returned X.  Returns the sweep count in *done.
 evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, double *X, int64_t ldx, double *lam,
-                        int sweeps, void *work, double *stats)
+                        int max_sweeps, double target, void *work, double *stats, int *done)
 {
     hipStream_t s = ctx->stream;
     RefWork w;
@@ -587,16 +649,38 @@ evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, 
     double *R = w.R, *AX = w.AX, *S = w.S, *Xn = w.Xn, *part = w.part;
     const dim3 g(OA_BLOCKS), t(256);
     std::vector<BigC> big;
-    for (int sw = 0; sw < sweeps; ++sw) {
+    int sw = 0;
+    for (;; ++sw) {
+        // R = I - X^T X (lower triangle computed, mirrored), A X
         hipLaunchKernelGGL(oa_eye_kernel, g, t, 0, s, n, R, n);
-        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, n, n, n, -1.0, X, ldx, X, ldx, 1.0, R, n, nullptr, 0));
+        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 1, n, n, n, -1.0, X, ldx, X, ldx, 1.0, R, n, nullptr, 0));
+        hipLaunchKernelGGL(oa_mirror_kernel, g, t, 0, s, n, R);
         EVD_CHECK(gemm_f64(s, OP_S, OP_N, 0, n, n, n, 1.0, A, lda, X, ldx, 0.0, AX, n, nullptr, 0));
-        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 0, n, n, n, 1.0, X, ldx, AX, n, 0.0, S, n, nullptr, 0));
+        // check of the current X
+        hipLaunchKernelGGL(oa_rayleigh_kernel, dim3((unsigned)n), dim3(64), 0, s, n, (const double *)AX,
+                           (const double *)X, ldx, lam);
+        hipLaunchKernelGGL(oa_resid_kernel, g, t, 0, s, n, (const double *)AX, (const double *)X,
+                           (const double *)lam, A, lda, part);
+        hipLaunchKernelGGL(oa_resid_final_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, n, (const double *)part,
+                           stats);
+        hipLaunchKernelGGL(oa_rnorm_kernel, g, t, 0, s, n, (const double *)R, part);
+        hipLaunchKernelGGL(oa_orth_final_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, n, (const double *)part,
+                           stats + 1);
+        if (sw >= max_sweeps) break;
+        if (target > 0.0) {
+            double h[2] = {0.0, 0.0};
+            EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, s)));
+            EVD_CHECK(evd_hip(ctx, hipStreamSynchronize(s)));
+            if (h[0] <= target && h[1] <= target) break;
+        }
+        // S = X^T (A X) (lower triangle computed, mirrored)
+        EVD_CHECK(gemm_f64(s, OP_T, OP_N, 1, n, n, n, 1.0, X, ldx, AX, n, 0.0, S, n, nullptr, 0));
+        hipLaunchKernelGGL(oa_mirror_kernel, g, t, 0, s, n, S);
         hipLaunchKernelGGL(oa_lambda_kernel, dim3(64), t, 0, s, n, (const double *)S, (const double *)R, lam);
         hipLaunchKernelGGL(oa_norms_kernel, g, t, 0, s, n, (const double *)S, (const double *)R, (const double *)lam,
                            part);
-        hipLaunchKernelGGL(oa_delta_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, n, (const double *)part, stats);
-        hipLaunchKernelGGL(oa_cluster_kernel, dim3(1), dim3(64), 0, s, n, (const double *)lam, (const double *)stats,
+        hipLaunchKernelGGL(oa_delta_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, n, (const double *)part, w.dl);
+        hipLaunchKernelGGL(oa_cluster_kernel, dim3(1), dim3(64), 0, s, n, (const double *)lam, (const double *)w.dl,
                            w.cid, w.cl, w.meta, w.big);
         // Rayleigh-Ritz on the clusters, then S' = Wbd^T S Wbd, R' = I - Wbd^T (I - R) Wbd
         const unsigned maxcl = (unsigned)(n / 2 < 1024 ? (n / 2 > 0 ? n / 2 : 1) : 1024);
@@ -616,23 +700,18 @@ evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, 
         // E' in the rotated basis, then F = Wbd (I + E') - I
         double *E = AX;  // A X is no longer needed
         hipLaunchKernelGGL(oa_e_kernel, g, t, 0, s, n, (const double *)S, (const double *)R, (const double *)lam,
-                           (const double *)stats, E);
+                           (const double *)w.dl, E);
         hipLaunchKernelGGL(oa_rowrot_kernel, gr, t, 0, s, n, E, (const int *)w.cl, (const int *)w.meta,
                            (const double *)w.Wg, 0);
         hipLaunchKernelGGL(oa_diagfix_kernel, dim3(maxcl), t, 0, s, E, n, (const int *)w.cl, (const int *)w.meta,
                            (const double *)w.Wg, 1);
         EVD_CHECK(big_clusters_end(ctx, n, E, w, big));
-        hipLaunchKernelGGL(oa_meta_stats_kernel, dim3(1), dim3(64), 0, s, (const int *)w.meta, stats);
         hipLaunchKernelGGL(oa_copy_kernel, g, t, 0, s, n, (const double *)X, ldx, Xn, n);
         EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, X, ldx, E, n, 1.0, Xn, n, nullptr, 0));
         hipLaunchKernelGGL(oa_copy_kernel, g, t, 0, s, n, (const double *)Xn, n, X, ldx);
     }
-    // residual of the final X with its Rayleigh quotients
-    EVD_CHECK(gemm_f64(s, OP_S, OP_N, 0, n, n, n, 1.0, A, lda, X, ldx, 0.0, AX, n, nullptr, 0));
-    hipLaunchKernelGGL(oa_rayleigh_kernel, dim3((unsigned)n), dim3(64), 0, s, n, (const double *)AX,
-                       (const double *)X, ldx, lam);
-    hipLaunchKernelGGL(oa_resid_kernel, g, t, 0, s, n, (const double *)AX, (const double *)X, (const double *)lam, A,
-                       lda, part);
-    hipLaunchKernelGGL(oa_resid_final_kernel, dim3(1), dim3(64), 0, s, OA_BLOCKS, n, (const double *)part, stats + 4);
+    hipLaunchKernelGGL(oa_meta_stats_kernel, dim3(1), dim3(64), 0, s, (const int *)w.meta, (const double *)w.dl, sw,
+                       stats);
+    if (done) *done = sw;
     return evd_hip(ctx, hipGetLastError());
 }

@@ -47,7 +47,7 @@ PROTOTYPES = {
     "evd_dsyevd": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
     "evd_dsyevd_noalloc": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _vp]),
     "evd_dsyevd_mixed_work_size": (_st, [_vp, _c, _c, _i64, _i64, ctypes.POINTER(_sz)]),
-    "evd_dsyevd_mixed": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _i32, _vp, _sz, _vp, _vp]),
+    "evd_dsyevd_mixed": (_st, [_vp, _c, _c, _i64, _vp, _i64, _vp, _i32, _d, _vp, _sz, _vp, _vp]),
     "evd_autotune_work_size": (_st, [_vp, _c, _i64, ctypes.POINTER(_sz)]),
     "evd_autotune": (_st, [_vp, _c, _i64, _vp, _i64, _vp, _sz, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_float)]),
     "evd_dsyevd_batched_work_size": (_st, [_vp, _c, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -217,10 +217,12 @@ class Context:
         self._check("evd_dsyevd_mixed_work_size", st)
         return b.value
 
-    def evd_dsyevd_mixed(self, jobz, uplo, n, A, lda, W, sweeps, work, work_bytes, info, stats=None):
+    def evd_dsyevd_mixed(self, jobz, uplo, n, A, lda, W, max_sweeps, target_residual, work, work_bytes, info,
+                         achieved=None):
         self.set_stream()
-        st = self.lib.evd_dsyevd_mixed(self.handle, _ch(jobz), _ch(uplo), n, _ptr(A), lda, _ptr(W), int(sweeps),
-                                       _ptr(work), work_bytes, _ptr(info), _ptr(stats))
+        st = self.lib.evd_dsyevd_mixed(self.handle, _ch(jobz), _ch(uplo), n, _ptr(A), lda, _ptr(W),
+                                       int(max_sweeps), float(target_residual), _ptr(work), work_bytes, _ptr(info),
+                                       _ptr(achieved))
         self._check("evd_dsyevd_mixed", st)
 
     def evd_autotune_work_size(self, jobz, n) -> int:
@@ -347,8 +349,11 @@ def context(device: int = 0) -> Context:
     return _default_ctx[device]
 
 
-def eigh_mixed(A, sweeps: int = 2, uplo: str = "L", b: int = 0, ctx: Context | None = None):
-    """``evd_dsyevd_mixed`` on a float64 GPU tensor: returns (w, Q, stats)."""
+def eigh_mixed(A, sweeps: int = 3, target: float = 0.0, uplo: str = "L", b: int = 0, ctx: Context | None = None,
+               check: bool = True):
+    """``evd_dsyevd_mixed`` on a float64 GPU tensor: returns (w, Q, achieved)
+    -- at most ``sweeps`` refinement sweeps, stopping early once the scaled
+    residual and orthogonality reach ``target`` (> 0)."""
     import torch
 
     n = A.shape[0]
@@ -361,8 +366,9 @@ def eigh_mixed(A, sweeps: int = 2, uplo: str = "L", b: int = 0, ctx: Context | N
     stats = torch.zeros(8, dtype=torch.float64, device=A.device)
     wb = ctx.evd_dsyevd_mixed_work_size("V", uplo, n, max(n, 1))
     work = torch.empty(max(wb, 256) // 8 + 32, dtype=torch.float64, device=A.device)
-    ctx.evd_dsyevd_mixed("V", uplo, n, Acm, max(n, 1), W, sweeps, work, wb, info, stats)
-    raise_for_info("evd_dsyevd_mixed", int(info.item()))
+    ctx.evd_dsyevd_mixed("V", uplo, n, Acm, max(n, 1), W, sweeps, target, work, wb, info, stats)
+    if check:
+        raise_for_info("evd_dsyevd_mixed", int(info.item()))
     return W[:n], Acm, stats
 
 

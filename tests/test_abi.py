@@ -136,3 +136,22 @@ def test_device_status_word_maps_to_errors():
         with pytest.raises(evd.EvdError) as e:
             evd.raise_for_info("f", info)
         assert e.value.status == status and e.value.arg == info
+
+
+def test_mixed_argument_checks(vctx):
+    """max_sweeps in 0..8, target_residual not NaN, workspace size: reported
+    on the host before any device work."""
+    lib, h = vctx
+    d = ctypes.c_double
+    args = lambda sweeps, target, wb: (h, b"V", b"L", ctypes.c_int64(10), ctypes.c_void_p(256), ctypes.c_int64(10),
+                                       ctypes.c_void_p(256), ctypes.c_int(sweeps), d(target), ctypes.c_void_p(256),
+                                       ctypes.c_size_t(wb), ctypes.c_void_p(256), None)
+    sz = ctypes.c_size_t()
+    assert lib.evd_dsyevd_mixed_work_size(h, b"V", b"L", ctypes.c_int64(10), ctypes.c_int64(10),
+                                          ctypes.byref(sz)) == evd.EVD_OK
+    assert lib.evd_dsyevd_mixed(*args(9, 0.0, sz.value)) == evd.EVD_ERR_INVALID_ARG
+    assert lib.evd_last_invalid_arg(h) == 8
+    assert lib.evd_dsyevd_mixed(*args(2, float("nan"), sz.value)) == evd.EVD_ERR_INVALID_ARG
+    assert lib.evd_last_invalid_arg(h) == 9
+    assert lib.evd_dsyevd_mixed(*args(2, 1e-13, sz.value - 1)) == evd.EVD_ERR_WORKSPACE
+    assert lib.evd_last_invalid_arg(h) == 11
