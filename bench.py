@@ -314,6 +314,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--overlap-ab", type=int, default=1,
+                    help="1 = after the timed steps, time one call with bulge chasing beside SBR (A/B)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision vs FP64 comparison at n = 16384 (run after the timed steps)")
     args = ap.parse_args()
@@ -460,6 +462,24 @@ def main():
             tr = abs(W.sum().item() - torch.trace(A0).item())
         out["accuracy"] = {"rho_res": round(res, 3), "rho_orth": round(orth, 3), "trace_err": tr}
 
+    if args.overlap_ab and args.jobz.upper() == "V":
+        # A/B: bulge chasing beside SBR (gated by the band columns SBR
+        # publishes) against the timed configuration (after SBR); one warm-up
+        # and one timed call with the overlap, after the timed steps
+        ctx.set_param("bc_overlap", 1)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        st = ctx.stage_times()
+        torch.cuda.synchronize()
+        t_ov = time.perf_counter() - t0
+        ctx.set_param("bc_overlap", 0)
+        out["bc_beside_sbr_ab"] = {
+            "after_sbr_ms": round(t * 1e3, 2), "after_sbr_sbr_plus_bc_ms": round(stage_ms[0] + stage_ms[1], 2),
+            "beside_sbr_ms": round(t_ov * 1e3, 2), "beside_sbr_sbr_plus_bc_ms": round(st[0] + st[1], 2),
+            "info": int(info.item())}
+        log(f"[bench] bc beside sbr: {out['bc_beside_sbr_ab']}")
     if not args.no_mixed and args.n == 32768:
         # the metric's second half: mixed precision + refinement against plain
         # FP64 at the 1e-13 scaled residual, on the mixed workload (n = 16384)

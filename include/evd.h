@@ -47,7 +47,8 @@ typedef enum {
     EVD_ERR_HIP = 3,           /* a HIP runtime call failed                   */
     EVD_ERR_NONFINITE = 4,     /* non-finite input (reported in device info)  */
     EVD_ERR_NOT_CONVERGED = 5, /* non-convergence (reported in device info)   */
-    EVD_ERR_NOT_IMPLEMENTED = 6
+    EVD_ERR_NOT_IMPLEMENTED = 6,
+    EVD_ERR_TIMEOUT = 7        /* a wait between workgroups gave up (device info) */
 } evd_status_t;
 
 /* ------------------------------------------------------------------ context */
@@ -95,6 +96,17 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "dc_max_iter"  iterations allowed per secular-equation root in D&C
  *                  (0 = 200); a small value forces the EVD_ERR_NOT_CONVERGED
  *                  status in `info` (for tests of the failure path)
+ *   "bc_overlap"   1 = bulge chasing runs beside SBR (Section 2.1.1, Alg. 1):
+ *                  launched on an auxiliary stream before the first panel,
+ *                  each of its steps waits until SBR has published the band
+ *                  columns it touches (panel by panel); 0 (default) = after
+ *                  SBR.  Results are bitwise the same either way.
+ *   "spin_limit_ms" longest wait (ms) of a workgroup for another workgroup's
+ *                  progress (bulge-chasing sweeps, SBR's published band, the
+ *                  panel-QR records) before the call gives up with
+ *                  EVD_ERR_TIMEOUT in `info` and NaN outputs (0 = 30000)
+ *   "debug_gate"   1 = bulge chasing waits for band columns that are never
+ *                  published (forces EVD_ERR_TIMEOUT; for tests of that path)
  * Unknown keys return EVD_ERR_INVALID_ARG. */
 evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value);
 evd_status_t evd_get_param(evd_ctx_t ctx, const char *key, int64_t *value /*[host]*/);
@@ -147,7 +159,9 @@ evd_status_t evd_sgemm_x3_work_size(evd_ctx_t ctx, int64_t m, int64_t n, int64_t
  *   info: one device int32 holding an evd_status_t: 0 on success,
  *     EVD_ERR_NONFINITE if the referenced triangle of A holds a NaN or an
  *       infinity (W, and A for jobz 'V', are then set to NaN),
- *     EVD_ERR_NOT_CONVERGED if a secular equation of D&C did not converge.
+ *     EVD_ERR_NOT_CONVERGED if a secular equation of D&C did not converge,
+ *     EVD_ERR_TIMEOUT if a wait between workgroups gave up ("spin_limit_ms";
+ *       W, and A for jobz 'V', are then set to NaN).
  *   The input scan and the status stay on the stream (no host round trip):
  *   the host return value reports only argument and runtime errors.
  *   work: at least evd_dsyevd_work_size() bytes, 256-byte aligned. */

@@ -16,6 +16,7 @@ const char *evd_status_string(evd_status_t s)
     case EVD_ERR_NONFINITE: return "non-finite input";
     case EVD_ERR_NOT_CONVERGED: return "not converged";
     case EVD_ERR_NOT_IMPLEMENTED: return "not implemented";
+    case EVD_ERR_TIMEOUT: return "wait between workgroups timed out";
     }
     return "unknown status";
 }
@@ -114,6 +115,9 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "last_hip_error")) return &ctx->last_hip_error;
     if (!strcmp(key, "capture_error")) return &ctx->capture_error;
     if (!strcmp(key, "dc_max_iter")) return &ctx->dc_max_iter;
+    if (!strcmp(key, "bc_overlap")) return &ctx->bc_overlap;
+    if (!strcmp(key, "spin_limit_ms")) return &ctx->spin_limit_ms;
+    if (!strcmp(key, "debug_gate")) return &ctx->debug_gate;
     return nullptr;
 }
 

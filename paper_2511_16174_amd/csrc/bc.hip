@@ -119,7 +119,8 @@ __host__ __device__ constexpr int bc_threads(int B) { return 16 * B < 64 ? 64 : 
 
 template <int B, typename T>
 __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int64_t ldab, T *V, T *TAU,
-                                                           int *prog, int store_v)
+                                                           int *prog, int store_v, const int *front, int *err,
+                                                           uint64_t limit)
 {
     constexpr int NT = bc_threads(B);
     constexpr int NW = NT / 64;
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int
     __shared__ T ws[B];
     __shared__ T red[NW];
     __shared__ T sh_tb[2];
+    __shared__ int sh_ok;
 
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
@@ -152,15 +154,22 @@ __global__ __launch_bounds__(bc_threads(B)) void bc_kernel(int64_t n, T *AB, int
         const int64_t Sprev = (c > 0) ? bc_steps(n, c - 1, B) : 0;
         T tprev = 0.0;
         for (int64_t s = 0; s < S; ++s) {
-            // wait for sweep c-1 to finish step s+1 (or all of its steps)
-            if (c > 0) {
-                const int need = (int)((s + 2 < Sprev) ? s + 2 : Sprev);
-                if (t == 0)
-                    while (ld_coh(&prog[c - 1]) < need) __builtin_amdgcn_s_sleep(1);
+            const int64_t r = c + 1 + s * B;
+            // wait (bounded) for sweep c-1 to finish step s+1 (or all of its
+            // steps) and, with SBR running beside, for the band columns up to
+            // r + B - 1 to be published; a wait that gives up raises *err and
+            // the whole launch leaves
+            if (c > 0 || front) {
+                if (t == 0) {
+                    bool ok = true;
+                    if (front) ok = wait_ge(front, (int)((r + B) < n ? (r + B) : n), err, limit);
+                    if (ok && c > 0) ok = wait_ge(&prog[c - 1], (int)((s + 2 < Sprev) ? s + 2 : Sprev), err, limit);
+                    sh_ok = ok ? 1 : 0;
+                }
                 __syncthreads();
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (!sh_ok) return;
             }
-            const int64_t r = c + 1 + s * B;
             const int64_t rp = r - B;
             const int m = (int)((n - r) < B ? (n - r) : B);
 
@@ -303,22 +312,28 @@ __global__ void bc_zero_v_kernel(T *V, T *TAU, int64_t nv, int64_t nt)
         TAU[i] = 0.0;
 }
 
+// bs == nullptr: cooperative launch on the context's stream; otherwise a
+// plain launch on bs of "bc_waves" workgroups (default: half the compute
+// units, leaving the rest to SBR running beside)
 template <int B, typename T>
 evd_status_t bc_launch(evd_ctx_t ctx, int64_t n, T *AB, int64_t ldab, T *V, T *TAU, int *prog,
-                       int store_v)
+                       int store_v, const int *front, int *err, hipStream_t bs)
 {
     int per_cu = 0;
     constexpr int NT = bc_threads(B);
     EVD_CHECK(evd_hip(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc_kernel<B, T>, NT, 0)));
     if (per_cu < 1) per_cu = 1;
     int64_t P = (int64_t)per_cu * ctx->num_cus;
+    if (bs && P > ctx->num_cus / 2) P = ctx->num_cus / 2;
     if (ctx->bc_waves > 0 && ctx->bc_waves < P) P = ctx->bc_waves;
     const int64_t nsweeps = n - 2;
     if (P > nsweeps) P = nsweeps;
     if (P < 1) P = 1;
-    void *args[] = {(void *)&n, &AB, (void *)&ldab, &V, &TAU, &prog, &store_v};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args, 0,
-                                              ctx->stream);
+    uint64_t limit = evd_spin_ticks(ctx);
+    void *args[] = {(void *)&n, &AB, (void *)&ldab, &V, &TAU, &prog, &store_v, (void *)&front, &err, &limit};
+    hipError_t e = bs ? hipLaunchKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args, 0, bs)
+                      : hipLaunchCooperativeKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args,
+                                                   0, ctx->stream);
     return evd_hip(ctx, e);
 }
 
@@ -327,49 +342,70 @@ evd_status_t bc_launch(evd_ctx_t ctx, int64_t n, T *AB, int64_t ldab, T *V, T *T
 // prog: n ints of scratch
 namespace {
 template <typename T>
-evd_status_t bc_run_t(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, T *AB, int64_t ldab, double *d, double *e, T *V,
-                      T *TAU, int *prog)
+evd_status_t bc_extract_t(evd_ctx_t ctx, int64_t n, const T *AB, int64_t ldab, double *d, double *e)
+{
+    hipLaunchKernelGGL(bc_extract_kernel<T>, dim3((unsigned)(evd_ceil_div(n, 256) < 1024 ? evd_ceil_div(n, 256) : 1024)),
+                       dim3(256), 0, ctx->stream, n, AB, ldab, d, e);
+    return evd_check_last();
+}
+
+// scratch reset on the context's stream, then the persistent kernel (on bs,
+// or cooperatively on the context's stream when bs is null)
+template <typename T>
+evd_status_t bc_start_t(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, T *AB, int64_t ldab, T *V, T *TAU, int *prog,
+                        int *err, const int *front, hipStream_t bs)
 {
     hipStream_t s = ctx->stream;
     const int store_v = (jobz == 'V' || jobz == 'v') ? 1 : 0;
-    if (n > 2) {
-        hipLaunchKernelGGL(bc_fill_int, dim3((unsigned)(evd_ceil_div(n, 256) < 1024 ? evd_ceil_div(n, 256) : 1024)),
-                           dim3(256), 0, s, prog, n, 0);
-        if (store_v) {
-            const int64_t steps = bc_num_steps(n, b);
-            const int64_t nv = steps * n * b, nt = steps * n;
-            hipLaunchKernelGGL(bc_zero_v_kernel<T>, dim3(4096), dim3(256), 0, s, V, TAU, nv, nt);
-        }
-        evd_status_t st;
-        switch (b) {
-        case 1: st = bc_launch<1, T>(ctx, n, AB, ldab, V, TAU, prog, store_v); break;
-        case 2: st = bc_launch<2, T>(ctx, n, AB, ldab, V, TAU, prog, store_v); break;
-        case 4: st = bc_launch<4, T>(ctx, n, AB, ldab, V, TAU, prog, store_v); break;
-        case 8: st = bc_launch<8, T>(ctx, n, AB, ldab, V, TAU, prog, store_v); break;
-        case 16: st = bc_launch<16, T>(ctx, n, AB, ldab, V, TAU, prog, store_v); break;
-        case 32: st = bc_launch<32, T>(ctx, n, AB, ldab, V, TAU, prog, store_v); break;
-        case 64: st = bc_launch<64, T>(ctx, n, AB, ldab, V, TAU, prog, store_v); break;
-        default: return EVD_ERR_INVALID_ARG;
-        }
-        if (st != EVD_OK) return st;
+    if (n <= 2) return EVD_OK;
+    hipLaunchKernelGGL(bc_fill_int, dim3((unsigned)(evd_ceil_div(n, 256) < 1024 ? evd_ceil_div(n, 256) : 1024)),
+                       dim3(256), 0, s, prog, n, 0);
+    if (store_v) {
+        const int64_t steps = bc_num_steps(n, b);
+        const int64_t nv = steps * n * b, nt = steps * n;
+        hipLaunchKernelGGL(bc_zero_v_kernel<T>, dim3(4096), dim3(256), 0, s, V, TAU, nv, nt);
     }
-    hipLaunchKernelGGL(bc_extract_kernel<T>, dim3((unsigned)(evd_ceil_div(n, 256) < 1024 ? evd_ceil_div(n, 256) : 1024)),
-                       dim3(256), 0, s, n, (const T *)AB, ldab, d, e);
-    return evd_check_last();
+    if (bs) {
+        EVD_CHECK(evd_hip(ctx, hipEventRecord(ctx->ev[10], s)));
+        EVD_CHECK(evd_hip(ctx, hipStreamWaitEvent(bs, ctx->ev[10], 0)));
+    }
+    switch (b) {
+    case 1: return bc_launch<1, T>(ctx, n, AB, ldab, V, TAU, prog, store_v, front, err, bs);
+    case 2: return bc_launch<2, T>(ctx, n, AB, ldab, V, TAU, prog, store_v, front, err, bs);
+    case 4: return bc_launch<4, T>(ctx, n, AB, ldab, V, TAU, prog, store_v, front, err, bs);
+    case 8: return bc_launch<8, T>(ctx, n, AB, ldab, V, TAU, prog, store_v, front, err, bs);
+    case 16: return bc_launch<16, T>(ctx, n, AB, ldab, V, TAU, prog, store_v, front, err, bs);
+    case 32: return bc_launch<32, T>(ctx, n, AB, ldab, V, TAU, prog, store_v, front, err, bs);
+    case 64: return bc_launch<64, T>(ctx, n, AB, ldab, V, TAU, prog, store_v, front, err, bs);
+    default: return EVD_ERR_INVALID_ARG;
+    }
 }
 
 }  // namespace
 
 evd_status_t bc_run(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, int64_t ldab, double *d, double *e,
-                    double *V, double *TAU, int *prog)
+                    double *V, double *TAU, int *prog, int *err, const int *front)
 {
-    return bc_run_t<double>(ctx, jobz, n, b, AB, ldab, d, e, V, TAU, prog);
+    EVD_CHECK(bc_start_t<double>(ctx, jobz, n, b, AB, ldab, V, TAU, prog, err, front, nullptr));
+    return bc_extract_t<double>(ctx, n, AB, ldab, d, e);
 }
 
-evd_status_t bc_run_f32(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, float *AB, int64_t ldab, double *d, double *e,
-                        float *V, float *TAU, int *prog)
+evd_status_t bc_run_f32(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, float *AB, int64_t ldab, double *d,
+                        double *e, float *V, float *TAU, int *prog, int *err, const int *front)
 {
-    return bc_run_t<float>(ctx, jobz, n, b, AB, ldab, d, e, V, TAU, prog);
+    EVD_CHECK(bc_start_t<float>(ctx, jobz, n, b, AB, ldab, V, TAU, prog, err, front, nullptr));
+    return bc_extract_t<float>(ctx, n, AB, ldab, d, e);
+}
+
+evd_status_t bc_launch_beside(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, int64_t ldab, double *V,
+                              double *TAU, int *prog, int *err, const int *front, hipStream_t bs)
+{
+    return bc_start_t<double>(ctx, jobz, n, b, AB, ldab, V, TAU, prog, err, front, bs);
+}
+
+evd_status_t bc_finish(evd_ctx_t ctx, int64_t n, const double *AB, int64_t ldab, double *d, double *e)
+{
+    return bc_extract_t<double>(ctx, n, AB, ldab, d, e);
 }
 
 extern "C" {
@@ -380,7 +416,7 @@ evd_status_t evd_dsb2st_work_size(evd_ctx_t ctx, int64_t n, size_t *bytes)
 {
     if (!ctx || !bytes) return EVD_ERR_INVALID_ARG;
     if (n < 0) { ctx->last_invalid_arg = 2; return EVD_ERR_INVALID_ARG; }
-    *bytes = evd_align256((size_t)(n > 0 ? n : 1) * sizeof(int));
+    *bytes = evd_align256((size_t)(n > 0 ? n : 1) * sizeof(int)) + 256;  // progress counters + the timeout word
     return EVD_OK;
 }
 
@@ -400,13 +436,15 @@ evd_status_t evd_dsb2st(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *
     else if (vec && n > 2 && !V) bad = 9;
     else if (vec && n > 2 && !TAU) bad = 10;
     else if (n > 0 && !work) bad = 11;
-    else if (work_bytes < (size_t)n * sizeof(int)) bad = 12;
+    else if (work_bytes < evd_align256((size_t)(n > 0 ? n : 1) * sizeof(int)) + 256) bad = 12;
     ctx->last_invalid_arg = bad;
     if (bad) return bad == 12 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
     EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
-    return bc_run(ctx, jobz, n, b, AB, ldab, d, e, V, TAU, (int *)work);
+    int *err = (int *)((char *)work + evd_align256((size_t)n * sizeof(int)));
+    hipLaunchKernelGGL(bc_fill_int, dim3(1), dim3(64), 0, ctx->stream, err, (int64_t)1, 0);
+    return bc_run(ctx, jobz, n, b, AB, ldab, d, e, V, TAU, (int *)work, err, nullptr);
 }
 
 }  // extern "C"

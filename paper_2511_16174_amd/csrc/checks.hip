@@ -9,12 +9,18 @@
 //           later kernel of the pipeline works on finite data and ends
 //           normally;
 //   end:    if the flag was raised, info = EVD_ERR_NONFINITE and the outputs
-//           (W, and the eigenvectors in A) are set to NaN.
+//           (W, and the eigenvectors in A) are set to NaN; likewise
+//           EVD_ERR_TIMEOUT if a wait between workgroups gave up (flag[2]).
 #include "common.h"
 
 namespace {
 
-__global__ void nf_clear_kernel(int *flag) { if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = 0; }
+// flag[0] non-finite input, [1] band columns published by SBR (bulge chasing
+// beside it), [2] a wait between workgroups gave up, [3] spare
+__global__ void nf_clear_kernel(int *flag)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 4) flag[threadIdx.x] = 0;
+}
 
 // Workgroups stride over columns, threads over the rows of the referenced
 // part of a column; the flag is written only by workgroups that met a
@@ -41,9 +47,9 @@ __global__ __launch_bounds__(256) void nf_zero_kernel(int64_t n, double *A, int6
 __global__ __launch_bounds__(256) void nf_finish_kernel(int64_t n, const int *flag, double *W, double *A, int64_t lda,
                                                         int vec, int32_t *info)
 {
-    if (!flag[0]) return;
+    if (!flag[0] && !flag[2]) return;
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && info) info[0] = EVD_ERR_NONFINITE;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && info) info[0] = flag[0] ? EVD_ERR_NONFINITE : EVD_ERR_TIMEOUT;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         W[i] = nan;
     if (vec)

@@ -129,6 +129,25 @@ __device__ __forceinline__ void grid_barrier_coh(int *bar, int G)
     __syncthreads();
 }
 
+// Bounded wait (one thread) until the device-coherent counter *p reaches
+// `need`: false if *err is raised meanwhile or `limit` ticks of the 100 MHz
+// wall clock pass (the waiter then raises *err itself, so every other waiter
+// of the launch gives up at its next poll instead of waiting its full limit).
+__device__ __forceinline__ bool wait_ge(const int *p, int need, int *err, uint64_t limit)
+{
+    if (ld_coh(p) >= need) return true;
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        if (ld_coh(p) >= need) return true;
+        if (ld_coh(err) != 0) return false;
+        if (wall_clock64() - t0 > limit) {
+            st_coh(err, 1);
+            return false;
+        }
+    }
+}
+
 // Agent-scope acquire / release on 32/64-bit flags in device memory.
 __device__ __forceinline__ int flag_load_acquire(const int *p)
 {
@@ -180,7 +199,18 @@ struct evd_ctx_s {
     int in_batch;             // 1 while the batched driver enqueues its matrices
     hipStream_t astream;      // auxiliary stream: BC-back T factors formed beside D&C
     int64_t dc_max_iter;      // iterations per secular root (0 = 200; lower values force non-convergence)
+    int64_t bc_overlap;       // 1 = bulge chasing beside SBR, gated by the published band columns
+    int64_t spin_limit_ms;    // longest inter-workgroup wait before EVD_ERR_TIMEOUT (0 = 30000)
+    int64_t debug_gate;       // 1 = bulge chasing waits on a band frontier that is never published
+    int plain_panels;         // internal: panel QR without a cooperative launch (while BC runs beside SBR)
 };
+
+// Wall-clock ticks (100 MHz) a workgroup may wait for another one.
+inline uint64_t evd_spin_ticks(const evd_ctx_s *ctx)
+{
+    const int64_t ms = ctx->spin_limit_ms > 0 ? ctx->spin_limit_ms : 30000;
+    return (uint64_t)ms * 100000ull;
+}
 
 // First failing HIP status seen on this host thread (internal helpers without
 // a context record here; the context reports it through "last_hip_error").
@@ -222,6 +252,35 @@ inline int64_t evd_choose_b(const evd_ctx_s *ctx, int64_t n)
 }
 
 // ---------------------------------------------------------------- internal API
+// SBR (sbr.hip).  err: device word raised when a wait between workgroups
+// gives up.  ov (optional): bulge chasing runs beside SBR -- SBR publishes
+// in *ov->front the number of leading band columns it has finished (panel by
+// panel, then n) and calls ov->launch(ov->arg) once the band storage is
+// initialised, before the first panel.
+struct SbrOverlap {
+    int *front;
+    evd_status_t (*launch)(void *arg);
+    void *arg;
+};
+evd_status_t sbr_run(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda, double *AB,
+                     int64_t ldab, double *T, void *work, int *err, const SbrOverlap *ov);
+evd_status_t sbr_run_f32(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, float *A, int64_t lda, float *AB,
+                         int64_t ldab, float *T, void *work, int *err, const SbrOverlap *ov);
+size_t sbr_work_bytes(int64_t n, int64_t b);
+size_t sbr_work_bytes_f32(int64_t n, int64_t b);
+// Bulge chasing (bc.hip).  front (optional): every step first waits until
+// *front covers the band columns it touches.  bc_run: the whole stage on the
+// context's stream (cooperative launch), then d, e.  bc_launch_beside: the
+// scratch is reset on the context's stream, then the persistent kernel is
+// launched (plain launch, "bc_waves" workgroups) on stream bs after it;
+// bc_finish extracts d, e once the caller has joined bs.
+evd_status_t bc_run(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, int64_t ldab, double *d, double *e,
+                    double *V, double *TAU, int *prog, int *err, const int *front);
+evd_status_t bc_run_f32(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, float *AB, int64_t ldab, double *d,
+                        double *e, float *V, float *TAU, int *prog, int *err, const int *front);
+evd_status_t bc_launch_beside(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, int64_t ldab, double *V,
+                              double *TAU, int *prog, int *err, const int *front, hipStream_t bs);
+evd_status_t bc_finish(evd_ctx_t ctx, int64_t n, const double *AB, int64_t ldab, double *d, double *e);
 // device address of the allocation-free entry point's scratch (noalloc.hip)
 evd_status_t noalloc_init_device(int device);
 // GEMM (gemm_f64.hip)

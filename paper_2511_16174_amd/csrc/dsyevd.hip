@@ -13,11 +13,6 @@
 // Eigenvalues only: SBR -> BC (no reflectors kept) -> bisection.
 #include "common.h"
 
-evd_status_t sbr_run(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda, double *AB,
-                     int64_t ldab, double *T, void *work);
-size_t sbr_work_bytes(int64_t n, int64_t b);
-evd_status_t bc_run(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *AB, int64_t ldab, double *d, double *e,
-                    double *V, double *TAU, int *prog);
 size_t dc_work_bytes(char compz, int64_t n);
 evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const double *e, double *W, double *Z,
                     int64_t ldz, void *work, int32_t *info);
@@ -90,6 +85,23 @@ __global__ void copy_kernel(int64_t n, const double *src, int64_t lds, double *d
     const int64_t total = n * n;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x)
         dst[(idx % n) + (idx / n) * ldd] = src[(idx % n) + (idx / n) * lds];
+}
+
+// Bulge chasing started beside SBR (SbrOverlap::launch): on the auxiliary
+// stream, after the band storage and BC's scratch are reset on the main one.
+struct BesideArg {
+    evd_ctx_t ctx;
+    char jobz;
+    int64_t n, b;
+    EvdWork *w;
+};
+evd_status_t launch_bc_beside(void *p)
+{
+    BesideArg *a = (BesideArg *)p;
+    EvdWork &w = *a->w;
+    EVD_CHECK(bc_launch_beside(a->ctx, a->jobz, a->n, a->b, w.AB, w.ldab, w.V, w.TAU, w.prog, w.nflag + 2,
+                               w.nflag + 1, a->ctx->astream));
+    return evd_hip(a->ctx, hipEventRecord(a->ctx->ev[11], a->ctx->astream));
 }
 
 __global__ void trivial_kernel(int64_t n, double *A, double *W, int vec, int32_t *info)
@@ -167,10 +179,28 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
     auto mark = [&](int i) { if (timing) (void)hipEventRecord(ctx->ev[i], s); };
 
     mark(0);
+    // w.nflag: [0] non-finite input, [1] band columns published by SBR, [2] timeout
     EVD_CHECK(nonfinite_begin(s, n, A, lda, uplo, w.nflag));
-    EVD_CHECK(sbr_run(ctx, uplo, n, b, A, lda, w.AB, w.ldab, w.T, w.sbr));
-    mark(1);
-    EVD_CHECK(bc_run(ctx, vec ? 'V' : 'N', n, b, w.AB, w.ldab, w.d, w.e, w.V, w.TAU, w.prog));
+    const bool beside = ctx->bc_overlap && ctx->astream && !ctx->in_batch && n > 2;
+    if (beside) {
+        // bulge chasing beside SBR (Section 2.1.1, Alg. 1): launched once SBR
+        // has reset the band, each step gated by the published band columns
+        BesideArg arg{ctx, vec ? 'V' : 'N', n, b, &w};
+        const SbrOverlap ov{w.nflag + 1, launch_bc_beside, &arg};
+        ctx->plain_panels = 1;
+        const evd_status_t st = sbr_run(ctx, uplo, n, b, A, lda, w.AB, w.ldab, w.T, w.sbr, w.nflag + 2, &ov);
+        ctx->plain_panels = 0;
+        EVD_CHECK(st);
+        mark(1);
+        EVD_CHECK(evd_hip(ctx, hipStreamWaitEvent(s, ctx->ev[11], 0)));
+        EVD_CHECK(bc_finish(ctx, n, w.AB, w.ldab, w.d, w.e));
+    } else {
+        EVD_CHECK(sbr_run(ctx, uplo, n, b, A, lda, w.AB, w.ldab, w.T, w.sbr, w.nflag + 2, nullptr));
+        mark(1);
+        // "debug_gate": wait for band columns nobody publishes (tests of the timeout path)
+        EVD_CHECK(bc_run(ctx, vec ? 'V' : 'N', n, b, w.AB, w.ldab, w.d, w.e, w.V, w.TAU, w.prog, w.nflag + 2,
+                         ctx->debug_gate ? w.nflag + 1 : nullptr));
+    }
     mark(2);
     if (!vec) {
         EVD_CHECK(dc_run(ctx, 'N', n, w.d, w.e, W, nullptr, 1, w.dc, info));

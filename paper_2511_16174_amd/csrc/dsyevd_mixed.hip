@@ -10,11 +10,6 @@
 //   X (FP64) -> RefSyEv sweeps (FP64 MFMA) -> eigenvectors, Rayleigh quotients
 #include "common.h"
 
-evd_status_t sbr_run_f32(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, float *A, int64_t lda, float *AB,
-                         int64_t ldab, float *T, void *work);
-size_t sbr_work_bytes_f32(int64_t n, int64_t b);
-evd_status_t bc_run_f32(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, float *AB, int64_t ldab, double *d, double *e,
-                        float *V, float *TAU, int *prog);
 size_t dc_work_bytes(char compz, int64_t n);
 evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const double *e, double *W, double *Z,
                     int64_t ldz, void *work, int32_t *info);
@@ -213,9 +208,9 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     EVD_CHECK(nonfinite_begin(s, n, A, lda, uplo, w.nflag));
     hipLaunchKernelGGL(mx_down_lower_kernel, g, t, 0, s, n, (const double *)A, lda, w.A32, up ? 1 : 0);
     if (up) hipLaunchKernelGGL(mx_mirror_upper_kernel, g, t, 0, s, n, A, lda);  // refinement reads the lower triangle
-    EVD_CHECK(sbr_run_f32(ctx, 'L', n, b, w.A32, n, w.AB, w.ldab, w.T, w.sbr));
+    EVD_CHECK(sbr_run_f32(ctx, 'L', n, b, w.A32, n, w.AB, w.ldab, w.T, w.sbr, w.nflag + 2, nullptr));
     mark(1);
-    EVD_CHECK(bc_run_f32(ctx, 'V', n, b, w.AB, w.ldab, w.d, w.e, w.V, w.TAU, w.prog));
+    EVD_CHECK(bc_run_f32(ctx, 'V', n, b, w.AB, w.ldab, w.d, w.e, w.V, w.TAU, w.prog, w.nflag + 2, nullptr));
     mark(2);
     EVD_CHECK(dc_run(ctx, 'I', n, w.d, w.e, w.lam, w.Qd, n, w.dc, info));
     hipLaunchKernelGGL(mx_down_kernel, g, t, 0, s, nn, (const double *)w.Qd, w.Qd32);

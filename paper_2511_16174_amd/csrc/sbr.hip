@@ -79,9 +79,10 @@ __device__ __forceinline__ T ll_value(const uint64_t (&w)[LL_WORDS<T>])
         return __builtin_bit_cast(T, (uint32_t)w[0]);
 }
 
-// one entry, polled until every word carries `epoch` (NaN if it never does)
+// one entry, polled until every word carries `epoch` (NaN, and *err raised,
+// if it never does)
 template <typename T>
-__device__ __forceinline__ T ll_load(const uint64_t *p, uint32_t epoch)
+__device__ __forceinline__ T ll_load(const uint64_t *p, uint32_t epoch, int *err)
 {
     uint64_t w[LL_WORDS<T>];
 #pragma unroll
@@ -98,6 +99,7 @@ __device__ __forceinline__ T ll_load(const uint64_t *p, uint32_t epoch)
         if (ok) return ll_value<T>(w);
         __builtin_amdgcn_s_sleep(1);
     }
+    st_coh(err, 2);
     return (T)__builtin_nan("");
 }
 
@@ -151,6 +153,25 @@ __global__ void extract_diag_blocks_kernel(int64_t n, int64_t b, int64_t tail0, 
     for (int64_t d = threadIdx.x; j + d < limit; d += blockDim.x) AB[d + j * ldab] = A[j + d + j * lda];
 }
 
+// Band columns j0 .. j1-1 (their diagonal-block part, as above) copied with
+// device-coherent stores by one workgroup, then the count of finished
+// leading band columns published in *front for bulge chasing running beside
+// SBR (after every store of the workgroup has completed).
+template <typename T>
+__global__ __launch_bounds__(256) void publish_band_kernel(int64_t n, int64_t b, int64_t j0, int64_t j1, int64_t tail0,
+                                                           const T *A, int64_t lda, T *AB, int64_t ldab, int *front,
+                                                           int value)
+{
+    for (int64_t j = j0 + threadIdx.y; j < j1; j += blockDim.y) {
+        int64_t limit = (j >= tail0) ? n : ((j / b) * b + b);
+        if (limit > n) limit = n;
+        for (int64_t d = threadIdx.x; j + d < limit; d += blockDim.x) st_coh(&AB[d + j * ldab], A[j + d + j * lda]);
+    }
+    mem_drain();
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) st_coh(front, value);
+}
+
 // Thread layout of the panel kernel's column phases: column cq gets TPC =
 // PANEL_THREADS / B threads; the first L = min(TPC, 64) of them are adjacent
 // lanes of one wavefront (their partial sums meet through lane shuffles),
@@ -193,7 +214,8 @@ template <int B, typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int chunk, T *P, int64_t lda,
                                                                  T *Y1, T *Y2, int64_t ldy, T *part,
                                                                  T *Sg, T *taus, T *Tout,
-                                                                 T *AB, int64_t ldab, int64_t j0, int epoch0)
+                                                                 T *AB, int64_t ldab, int64_t j0, int epoch0,
+                                                                 int *err)
 {
     // Workgroup g holds rows r0 .. r0 + chunk - 1 of the m x B panel in
     // registers.  Per column j: (1) the owners of column j put it in LDS;
@@ -315,11 +337,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
                     }
 #pragma unroll
                     for (int u = 0; u < 8; ++u) s2 += ll_value<T>(wd[u]);
-                    if (!ok) s2 = (T)__builtin_nan("");  // never written: poison, do not hang
+                    if (!ok) {  // never written: poison, report, do not hang
+                        s2 = (T)__builtin_nan("");
+                        st_coh(err, 2);
+                    }
                 }
                 scr[w * B + lane] = s2;
             }
-            if (tid < B) topsh[tid] = ll_load<T>(&rec[((size_t)B + tid) * LL_WORDS<T>], (uint32_t)E);
+            if (tid < B) topsh[tid] = ll_load<T>(&rec[((size_t)B + tid) * LL_WORDS<T>], (uint32_t)E, err);
             __syncthreads();
             if (tid < B) {
                 T r = 0.0;
@@ -414,7 +439,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
 
 template <int B, typename T>
 evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
-                          T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int epoch0)
+                          T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int epoch0, int *err)
 {
     // Automatic: as few workgroups as the registers allow (CH rows each):
     // every workgroup reads every record of a column, so the exchange grows
@@ -435,24 +460,32 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T 
     const size_t lds = 0;
     int chunk_i = (int)chunk;
     void *args[] = {&m, &chunk_i, &P, (void *)&lda, &Y1, &Y2, (void *)&ldy, &part, &Sg, &taus, &Tout, &AB,
-                    (void *)&ldab, (void *)&j0, &epoch0};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3((unsigned)G), dim3(PANEL_THREADS), args,
-                                              (unsigned)lds, ctx->stream);
+                    (void *)&ldab, (void *)&j0, &epoch0, &err};
+    // while bulge chasing runs beside SBR the panel is a plain launch (its at
+    // most PANEL_MAX_WGS workgroups find free compute units: the previous
+    // kernels of the stream have finished and bulge chasing holds at most
+    // "bc_waves" of them); its record polls are bounded either way
+    hipError_t e = ctx->plain_panels
+                       ? hipLaunchKernel((const void *)panel_qr_kernel<B, T>, dim3((unsigned)G), dim3(PANEL_THREADS),
+                                         args, lds, ctx->stream)
+                       : hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3((unsigned)G),
+                                                    dim3(PANEL_THREADS), args, (unsigned)lds, ctx->stream);
     return evd_hip(ctx, e);
 }
 
 template <typename T>
 evd_status_t panel_dispatch(evd_ctx_t ctx, int64_t b, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
-                            T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int epoch0)
+                            T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int epoch0,
+                            int *err)
 {
     switch (b) {
-    case 1: return launch_panel<1, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
-    case 2: return launch_panel<2, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
-    case 4: return launch_panel<4, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
-    case 8: return launch_panel<8, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
-    case 16: return launch_panel<16, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
-    case 32: return launch_panel<32, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
-    case 64: return launch_panel<64, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0);
+    case 1: return launch_panel<1, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0, err);
+    case 2: return launch_panel<2, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0, err);
+    case 4: return launch_panel<4, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0, err);
+    case 8: return launch_panel<8, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0, err);
+    case 16: return launch_panel<16, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0, err);
+    case 32: return launch_panel<32, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0, err);
+    case 64: return launch_panel<64, T>(ctx, m, P, lda, Y1, Y2, ldy, part, Sg, taus, Tout, AB, ldab, j0, epoch0, err);
     default: return EVD_ERR_INVALID_ARG;
     }
 }
@@ -545,7 +578,7 @@ inline dim3 grid_for(int64_t count)
 // q = 1 this is the single-blocked scheme of Eq. 1.
 template <typename T>
 evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int64_t lda, T *AB, int64_t ldab,
-                       T *Tf, void *work)
+                       T *Tf, void *work, int *err, const SbrOverlap *ov)
 {
     hipStream_t s = ctx->stream;
     SbrWork<T> w;
@@ -573,6 +606,12 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
     };
     mirror(b);
     const int64_t p = evd_sbr_num_panels(n, b);
+    // bulge chasing beside SBR: started once the band storage is zeroed
+    if (ov) EVD_CHECK(ov->launch(ov->arg));
+    auto publish = [&](int64_t j0, int64_t j1, int64_t value) {
+        hipLaunchKernelGGL(publish_band_kernel<T>, dim3(1), dim3(64, 4), 0, s, n, b, j0, j1, p * b, (const T *)A,
+                           lda, AB, ldab, ov->front, (int)value);
+    };
     const int64_t q = (ctx->sbr_nb > 0) ? ((ctx->sbr_nb / b) > 0 ? ctx->sbr_nb / b : 1)
                                         : ((SBR_NB / b) > 0 ? SBR_NB / b : 1);
     const int64_t qmax = w.q < q ? w.q : q;  // the accumulators hold w.q panels
@@ -600,7 +639,10 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
             T *P = A + i0 + j0 * lda;
             T *A2 = A + i0 + i0 * lda;
             EVD_CHECK(panel_dispatch<T>(ctx, b, m, P, lda, Y, w.ZY + ro + (2 * t + 1) * b * ldc, ldc, w.part, w.Sg,
-                                        w.taus, Tk, AB, ldab, j0, (int)(k * (b + 1))));
+                                        w.taus, Tk, AB, ldab, j0, (int)(k * (b + 1)), err));
+            // the panel's band columns are final: its diagonal block was brought
+            // up to date before the QR, and R is in the band
+            if (ov) publish(j0, j0 + b, j0 + b);
             // W = Y T
             EVD_CHECK(gemm_t(s, OP_N, OP_N, 0, m, b, b, (T)1, Y, ldc, Tk, b, (T)0, w.W, m, (T *)nullptr, 0));
             // X = A_2 W (stale A_2 inside the block) into the Z slot
@@ -628,7 +670,9 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
                              A + iK + iK * lda, lda, (T *)nullptr, 0));
         }
     }
-    {
+    if (ov) {
+        publish(p * b, n, n);   // the trailing block, final after the last update
+    } else {
         dim3 blk(64, 4);
         hipLaunchKernelGGL(extract_diag_blocks_kernel<T>, dim3((unsigned)evd_ceil_div(n, 4)), blk, 0, s, n, b, p * b,
                            (const T *)A, lda, AB, ldab);
@@ -639,15 +683,15 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
 }  // namespace
 
 evd_status_t sbr_run(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *A, int64_t lda, double *AB,
-                     int64_t ldab, double *T, void *work)
+                     int64_t ldab, double *T, void *work, int *err, const SbrOverlap *ov)
 {
-    return sbr_run_t<double>(ctx, uplo, n, b, A, lda, AB, ldab, T, work);
+    return sbr_run_t<double>(ctx, uplo, n, b, A, lda, AB, ldab, T, work, err, ov);
 }
 
 evd_status_t sbr_run_f32(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, float *A, int64_t lda, float *AB,
-                         int64_t ldab, float *T, void *work)
+                         int64_t ldab, float *T, void *work, int *err, const SbrOverlap *ov)
 {
-    return sbr_run_t<float>(ctx, uplo, n, b, A, lda, AB, ldab, T, work);
+    return sbr_run_t<float>(ctx, uplo, n, b, A, lda, AB, ldab, T, work, err, ov);
 }
 
 size_t sbr_work_bytes(int64_t n, int64_t b) { return sbr_layout<double>(n, b, nullptr, nullptr); }
@@ -666,7 +710,7 @@ evd_status_t evd_dsy2sb_work_size(evd_ctx_t ctx, int64_t n, int64_t b, size_t *b
     if (!ctx || !bytes) return EVD_ERR_INVALID_ARG;
     if (n < 0) { ctx->last_invalid_arg = 2; return EVD_ERR_INVALID_ARG; }
     if (b < 1 || b > 64 || (64 % b) != 0) { ctx->last_invalid_arg = 3; return EVD_ERR_INVALID_ARG; }
-    *bytes = sbr_work_bytes(n, b);
+    *bytes = sbr_work_bytes(n, b) + 256;   // + the word a timed-out wait raises
     return EVD_OK;
 }
 
@@ -684,13 +728,15 @@ evd_status_t evd_dsy2sb(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *
     else if (ldab < 2 * b + 1) bad = 8;
     else if (evd_sbr_num_panels(n, b) > 0 && !T) bad = 9;
     else if (n > 0 && !work) bad = 10;
-    else if (work_bytes < sbr_work_bytes(n, b)) bad = 11;
+    else if (work_bytes < sbr_work_bytes(n, b) + 256) bad = 11;
     ctx->last_invalid_arg = bad;
     if (bad) return bad == 11 ? EVD_ERR_WORKSPACE : EVD_ERR_INVALID_ARG;
     if (n == 0) return EVD_OK;
     if (ctx->device < 0) return EVD_ERR_HIP;
     EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
-    return sbr_run(ctx, uplo, n, b, A, lda, AB, ldab, T, work);
+    int *err = (int *)((char *)work + sbr_work_bytes(n, b));
+    hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(64), 0, ctx->stream, err, (int64_t)1, 0);
+    return sbr_run(ctx, uplo, n, b, A, lda, AB, ldab, T, work, err, nullptr);
 }
 
 }  // extern "C"

@@ -23,6 +23,7 @@ EVD_ERR_HIP = 3
 EVD_ERR_NONFINITE = 4
 EVD_ERR_NOT_CONVERGED = 5
 EVD_ERR_NOT_IMPLEMENTED = 6
+EVD_ERR_TIMEOUT = 7
 
 _i64, _i32, _sz, _d, _c, _vp = (ctypes.c_int64, ctypes.c_int, ctypes.c_size_t, ctypes.c_double,
                                  ctypes.c_char, ctypes.c_void_p)
@@ -325,7 +326,7 @@ def raise_for_info(func: str, info: int):
     """Raise EvdError for a nonzero device status word (an evd_status_t:
     EVD_ERR_NONFINITE or EVD_ERR_NOT_CONVERGED)."""
     if info != 0:
-        status = info if info in (EVD_ERR_NONFINITE, EVD_ERR_NOT_CONVERGED) else EVD_ERR_NOT_CONVERGED
+        status = info if info in (EVD_ERR_NONFINITE, EVD_ERR_NOT_CONVERGED, EVD_ERR_TIMEOUT) else EVD_ERR_NOT_CONVERGED
         raise EvdError(func, status, info)
 
 

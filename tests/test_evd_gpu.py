@@ -307,3 +307,51 @@ def test_forced_dc_nonconvergence_reports_status():
     w, Q, info = raw_dsyevd(ctx, A)
     assert info == 0
     check(A, w, Q, oracle.syev(A, jobz="N"))
+
+
+@pytest.mark.parametrize("n,b,jobz", [(300, 32, "V"), (1000, 32, "V"), (2100, 64, "V"), (2100, 64, "N"),
+                                      (8192, 64, "V")])
+def test_bc_beside_sbr_matches_bc_after_sbr(n, b, jobz):
+    """Bulge chasing started beside SBR ("bc_overlap" = 1, gated by the band
+    columns SBR publishes panel by panel) computes exactly what it computes
+    after SBR: eigenvalues and eigenvectors agree bit for bit, and both meet
+    the oracle's gates."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    A = W.gaussian_sym(n, seed=70 + n + b)
+    out = []
+    for ov in (0, 1):
+        with params(ctx, bc_overlap=ov, b=b):
+            w, Q, info = raw_dsyevd(ctx, A, jobz=jobz)
+        assert info == 0
+        out.append((w, Q))
+    (w0, Q0), (w1, Q1) = out
+    assert np.array_equal(w0, w1)
+    if jobz == "V":
+        assert np.array_equal(Q0, Q1)
+        if n <= 2100:
+            check(A, w1, Q1, oracle.syev(A, jobz="N"))
+    else:
+        assert M.eig_error(w1, oracle.syev(A, jobz="N")) <= ETA
+
+
+@pytest.mark.parametrize("jobz", ["N", "V"])
+def test_bc_wait_timeout_reports_status(jobz):
+    """"debug_gate" makes bulge chasing wait for band columns that are never
+    published, with a 2 ms limit: every workgroup leaves, the call reports
+    EVD_ERR_TIMEOUT with NaN outputs, and the context works normally
+    afterwards."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    n = 700
+    A = W.gaussian_sym(n, seed=77)
+    with params(ctx, debug_gate=1, spin_limit_ms=2):
+        w, Q, info = raw_dsyevd(ctx, A, jobz=jobz)
+    assert info == evd.EVD_ERR_TIMEOUT
+    assert np.all(np.isnan(w))
+    if jobz == "V":
+        assert np.all(np.isnan(Q))
+    w, Q, info = raw_dsyevd(ctx, A, jobz=jobz)
+    assert info == 0
+    if jobz == "V":
+        check(A, w, Q, oracle.syev(A, jobz="N"))
