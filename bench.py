@@ -106,6 +106,32 @@ def known_logspaced_gpu(n: int, seed: int, reflectors: int = 64):
     return A.contiguous(), lam
 
 
+def known_uniform_inplace(n: int, seed: int, reflectors: int = 64):
+    """A = H_1 ... H_64 diag(lam) H_64 ... H_1 with lam uniform on [-1, 1]
+    (the recipe of workloads.known_spectrum('uniform'); same PCG64 draws in
+    the same order), assembled on the GPU without n x n temporaries (a
+    matrix of 77 GB at n = 98304): per reflector p = A v, w = p - (v.p) v,
+    then the rank-2 update A -= 2 (v w^T + w v^T) in place."""
+    import numpy as np
+    import torch
+    from paper_2511_16174_amd import workloads
+
+    r = workloads.rng(seed)
+    V = workloads.reflector_vectors(n, reflectors, r)
+    lam = np.sort(r.uniform(-1.0, 1.0, size=n))
+    A = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    A.diagonal().copy_(torch.from_numpy(lam))
+    for v in V[::-1]:
+        v = torch.from_numpy(v / np.linalg.norm(v)).cuda()
+        p = torch.mv(A, v)
+        w = p - torch.dot(v, p) * v
+        L = torch.stack([v, w], dim=1)
+        R = torch.stack([w, v], dim=0)
+        A.addmm_(L, R, alpha=-2.0)
+    torch.cuda.synchronize()
+    return A, lam
+
+
 def mixed_vs_fp64(n: int = 16384, seed: int = 5, reps: int = 2, max_sweeps: int = 8, target: float = 1e-13):
     """Mixed precision + FP64 refinement against plain FP64 on the mixed
     workload (log-spaced known spectrum, 64 reflectors), both with vectors and
@@ -303,6 +329,10 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--b", type=int, default=64)
     ap.add_argument("--jobz", default="V")
+    ap.add_argument("--matrix", default="gaussian", choices=["gaussian", "known-uniform"],
+                    help="known-uniform: lam uniform on [-1, 1] around 64 reflectors, built in place "
+                         "(eigenvalue error reported against the known lam)")
+    ap.add_argument("--seed", type=int, default=3, help="seed of the known-spectrum matrix")
     ap.add_argument("--order", type=int, default=1,
                     help="0 = reordered stages (Q_s H.. then Q_sb Q_d), 1 = conventional (Q_s (H.. Q_d))")
     ap.add_argument("--bcback-valu", type=int, default=0,
@@ -352,12 +382,17 @@ def main():
     ctx.set_param("order", args.order)
     ctx.set_param("bcback_valu", args.bcback_valu)
 
-    log(f"[bench] generating n={n} on the GPU")
-    g = torch.Generator(device=dev)
-    g.manual_seed(3)
-    G = torch.randn((n, n), dtype=torch.float64, device=dev, generator=g)
-    A0 = (G + G.t()) * (0.5 / n ** 0.5)   # symmetric: row-major == column-major
-    del G
+    lam_known = None
+    if args.matrix == "known-uniform":
+        log(f"[bench] building the known-spectrum matrix n={n} in place on the GPU")
+        A0, lam_known = known_uniform_inplace(n, seed=args.seed)
+    else:
+        log(f"[bench] generating n={n} on the GPU")
+        g = torch.Generator(device=dev)
+        g.manual_seed(3)
+        G = torch.randn((n, n), dtype=torch.float64, device=dev, generator=g)
+        A0 = (G + G.t()) * (0.5 / n ** 0.5)   # symmetric: row-major == column-major
+        del G
     A = torch.empty_like(A0)
     W = torch.empty(n, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -424,6 +459,9 @@ def main():
         roofline = None
 
     what = "with eigenvectors" if args.jobz.upper() == "V" else "eigenvalues only"
+    wl = (f"plain FP64 EVD {what}, n={n}, A=(G+G^T)/(2 sqrt n), G iid N(0,1)" if lam_known is None else
+          f"plain FP64 EVD {what}, n={n}, known spectrum: lam uniform on [-1,1], Q from 64 Householder "
+          f"reflectors (seed {args.seed})")
     out = {
         "metric": f"EVD TFLOPS (4n^3/3) and time-to-solution, plain FP64 {what}",
         "value": round(value, 4),
@@ -440,8 +478,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"plain FP64 EVD {what}, n={n}, A=(G+G^T)/(2 sqrt n), G iid N(0,1)",
-                   "n": n, "b": b, "jobz": args.jobz, "uplo": "L", "seed": 3,
+        "config": {"workload": wl,
+                   "n": n, "b": b, "jobz": args.jobz, "uplo": "L", "seed": 3 if lam_known is None else args.seed,
                    "stage_order": "reordered" if args.order == 0 else "conventional"},
         "stage_ms": stages,
         "roofline": roofline,
@@ -462,6 +500,13 @@ def main():
             tr = abs(W.sum().item() - torch.trace(A0).item())
         out["accuracy"] = {"rho_res": round(res, 3), "rho_orth": round(orth, 3), "trace_err": tr}
 
+    if lam_known is not None:
+        lam_t = torch.from_numpy(lam_known).to(dev)
+        out["accuracy_known_spectrum"] = {
+            "eig_error": (torch.max(torch.abs(W - lam_t)) / torch.max(torch.abs(lam_t))).item(),
+            "trace_err": abs(W.sum().item() - float(lam_known.sum())),
+            "ascending": bool((W[1:] >= W[:-1]).all().item())}
+        log(f"[bench] known spectrum: {out['accuracy_known_spectrum']}")
     if args.overlap_ab and args.jobz.upper() == "V":
         # A/B: bulge chasing beside SBR (gated by the band columns SBR
         # publishes) against the timed configuration (after SBR); one warm-up

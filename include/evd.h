@@ -155,7 +155,7 @@ evd_status_t evd_sgemm_x3_work_size(evd_ctx_t ctx, int64_t m, int64_t n, int64_t
  *   jobz 'V': eigenvalues -> W and orthonormal eigenvectors -> A (column i
  *             pairs with W[i]).
  *   uplo 'L' or 'U': the triangle of A that is read.
- *   A: n x n, lda >= max(1, n).  W: n doubles.
+ *   A: n x n, max(1, n) <= lda <= EVD_MAX_N.  W: n doubles.
  *   info: one device int32 holding an evd_status_t: 0 on success,
  *     EVD_ERR_NONFINITE if the referenced triangle of A holds a NaN or an
  *       infinity (W, and A for jobz 'V', are then set to NaN),
@@ -165,6 +165,7 @@ evd_status_t evd_sgemm_x3_work_size(evd_ctx_t ctx, int64_t m, int64_t n, int64_t
  *   The input scan and the status stay on the stream (no host round trip):
  *   the host return value reports only argument and runtime errors.
  *   work: at least evd_dsyevd_work_size() bytes, 256-byte aligned. */
+#define EVD_MAX_N ((int64_t)1 << 21) /* largest n and lda: the tile loaders' 32-bit byte offsets */
 evd_status_t evd_dsyevd_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n, int64_t lda,
                                   size_t *bytes /*[host]*/);
 evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *A, int64_t lda,

@@ -139,8 +139,8 @@ evd_status_t evd_dsyevd_work_size(evd_ctx_t ctx, char jobz, char uplo, int64_t n
     int bad = 0;
     if (!(vec || jobz == 'N' || jobz == 'n')) bad = 2;
     else if (!(uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u')) bad = 3;
-    else if (n < 0) bad = 4;
-    else if (lda < (n > 1 ? n : 1)) bad = 5;
+    else if (n < 0 || n > EVD_MAX_N) bad = 4;
+    else if (lda < (n > 1 ? n : 1) || lda > EVD_MAX_N) bad = 5;
     ctx->last_invalid_arg = bad;
     if (bad) return EVD_ERR_INVALID_ARG;
     *bytes = evd_layout(n, choose_b(ctx, n), vec, nullptr, nullptr);
@@ -156,9 +156,9 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
     int bad = 0;
     if (!(vec || jobz == 'N' || jobz == 'n')) bad = 2;
     else if (!(uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u')) bad = 3;
-    else if (n < 0) bad = 4;
+    else if (n < 0 || n > EVD_MAX_N) bad = 4;
     else if (n > 0 && !A) bad = 5;
-    else if (lda < (n > 1 ? n : 1)) bad = 6;
+    else if (lda < (n > 1 ? n : 1) || lda > EVD_MAX_N) bad = 6;
     else if (n > 0 && !W) bad = 7;
     else if (n > 0 && !work) bad = 8;
     else if (work_bytes < evd_layout(n, b, vec, nullptr, nullptr)) bad = 9;

@@ -155,3 +155,20 @@ def test_mixed_argument_checks(vctx):
     assert lib.evd_last_invalid_arg(h) == 9
     assert lib.evd_dsyevd_mixed(*args(2, 1e-13, sz.value - 1)) == evd.EVD_ERR_WORKSPACE
     assert lib.evd_last_invalid_arg(h) == 11
+
+
+def test_size_limits(vctx):
+    """n and lda above EVD_MAX_N (2^21: the tile loaders keep byte offsets in
+    32 bits) are rejected on the host, before any device work; the largest
+    sizes that fit in 288 GB (n = 98304, eigenvalues only) are accepted."""
+    lib, h = vctx
+    sz = ctypes.c_size_t()
+    big = (1 << 21) + 1
+    assert lib.evd_dsyevd_work_size(h, b"N", b"L", big, big, ctypes.byref(sz)) == evd.EVD_ERR_INVALID_ARG
+    assert lib.evd_last_invalid_arg(h) == 4
+    assert lib.evd_dsyevd_work_size(h, b"N", b"L", 1000, big, ctypes.byref(sz)) == evd.EVD_ERR_INVALID_ARG
+    assert lib.evd_last_invalid_arg(h) == 5
+    assert lib.evd_dsyevd_work_size(h, b"N", b"L", 98304, 98304, ctypes.byref(sz)) == evd.EVD_OK
+    assert sz.value < 8 * 2**30          # eigenvalues only: O(n b) scratch besides A
+    assert lib.evd_dsyevd_work_size(h, b"V", b"L", 98304, 98304, ctypes.byref(sz)) == evd.EVD_OK
+    assert sz.value > 288 * 10**9        # with vectors it would not fit one GPU
