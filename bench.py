@@ -235,13 +235,18 @@ def batched_main(args):
     p50 / p99 by nearest rank of (end - start) and of (end - first start of
     the batch); aggregate TFLOPS = sum 4 n^3 / 3 over the batch / wall time."""
     import numpy as np
+    # independent streams need hardware queues of their own to run side by
+    # side: HIP maps a process's streams onto GPU_MAX_HW_QUEUES of them (4 by
+    # default); read when the runtime starts, so set before the first HIP call
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import torch
     from paper_2511_16174_amd import evd, workloads
 
     ctx = evd.context(0)
     ctx.set_param("b", 0)
-    ctx.set_param("batch_graph", 1)
+    ctx.set_param("batch_graph", args.batch_graph)
     ctx.set_param("batch_streams", args.batch_streams)
+    ctx.set_param("batch_plain", args.batch_plain)
     Ls, mats = workloads.tight_binding_batch(256, 7, 8, 45)
     ns = [m.shape[0] for m in mats]
     pristine = [torch.from_numpy(np.ascontiguousarray(m.T)).cuda() for m in mats]
@@ -311,7 +316,9 @@ def batched_main(args):
         "data": "synthetic",
         "config": {"workload": "256 tight-binding Hamiltonians, L x L tori, L ~ U{8..45}, hopping -1, "
                                "on-site U[-2,2], seed 7, with vectors",
-                   "batch": len(ns), "n_min": min(ns), "n_max": max(ns), "streams": args.batch_streams},
+                   "batch": len(ns), "n_min": min(ns), "n_max": max(ns), "streams": args.batch_streams,
+                   "plain_launches": args.batch_plain, "graph": args.batch_graph,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "latency_ms": {"p50": round(pct(lat, 50), 3), "p99": round(pct(lat, 99), 3),
                        "p50_from_batch_start": round(pct(lat_launch, 50), 3),
                        "p99_from_batch_start": round(pct(lat_launch, 99), 3)},
@@ -338,7 +345,12 @@ def main():
     ap.add_argument("--bcback-valu", type=int, default=0,
                     help="1 = reflector-by-reflector BC-back on the vector ALUs instead of the blocked MFMA kernel")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed", "batched"])
-    ap.add_argument("--batch-streams", type=int, default=4, help="internal streams of the batched driver")
+    ap.add_argument("--batch-streams", type=int, default=8, help="internal streams of the batched driver")
+    ap.add_argument("--batch-graph", type=int, default=0, help="1 = replay the batch as one captured hipGraph")
+    ap.add_argument("--hw-queues", type=int, default=16, choices=range(1, 17), metavar="1..16",
+                    help="batched mode: hardware queues of the process (GPU_MAX_HW_QUEUES)")
+    ap.add_argument("--batch-plain", type=int, default=1,
+                    help="1 = the batched driver's persistent kernels use plain (not cooperative) launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain 1 GiB device copy (the reference kernel for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc pass)")

@@ -92,7 +92,7 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "last_hip_error" first HIP error code a call met (read; set 0 to clear)
  *   "capture_error"  HIP error that made the last batched graph capture fall
  *                  back to a direct run (read only)
- *   "batch_streams", "batch_graph", "last_graph_used"  see evd_dsyevd_batched
+ *   "batch_streams", "batch_graph", "batch_plain", "last_graph_used"  see evd_dsyevd_batched
  *   "dc_max_iter"  iterations allowed per secular-equation root in D&C
  *                  (0 = 200); a small value forces the EVD_ERR_NOT_CONVERGED
  *                  status in `info` (for tests of the failure path)
@@ -240,10 +240,14 @@ evd_status_t evd_autotune(evd_ctx_t ctx, char jobz, int64_t n, const double *A, 
  * t_start_end (optional): device uint64[2*batch], wall_clock64 (100 MHz) ticks
  * at the start and end of every matrix.
  * Matrices are ordered by decreasing n^3 and spread over "batch_streams"
- * (default 4) streams; the launch sequence is captured once into a hipGraph
- * ("batch_graph" = 1, default) and replayed while sizes and pointers are
- * unchanged ("last_graph_used" reports whether the graph ran).  Persistent
- * kernels are capped at (compute units / streams) workgroups each.
+ * (default 8) streams, launched directly (default) or, with "batch_graph" =
+ * 1, captured once into a hipGraph that is replayed while sizes and pointers
+ * are unchanged ("last_graph_used" reports whether the graph ran; on ROCm 7
+ * the replay runs the streams' branches one after another, 2.2x slower than
+ * the direct launches on the tight-binding batch).  Persistent kernels are
+ * capped at (compute units / streams) workgroups each and, with
+ * "batch_plain" = 1 (default), launched plainly so that the streams run side
+ * by side (0 = cooperative launches, which the runtime serialises).
  * work: evd_dsyevd_batched_work_size() bytes. */
 evd_status_t evd_dsyevd_batched_work_size(evd_ctx_t ctx, char jobz, int32_t batch, const int64_t *n /*[host]*/,
                                           const int64_t *lda /*[host]*/, size_t *bytes /*[host]*/);

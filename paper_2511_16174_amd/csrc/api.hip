@@ -41,7 +41,8 @@ evd_status_t evd_create(evd_ctx_t *ctx, int device)
     memset(c, 0, sizeof(*c));
     c->device = device;
     c->stream = nullptr;
-    c->batch_graph = 1;
+    c->batch_graph = 0;   // direct launches: the graph's replay runs the streams' branches one after another
+    c->batch_plain = 1;
     c->order = 1;  // conventional stage order: fewest flops when the stages run one after another
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) { delete c; return EVD_ERR_HIP; }
@@ -118,6 +119,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "bc_overlap")) return &ctx->bc_overlap;
     if (!strcmp(key, "spin_limit_ms")) return &ctx->spin_limit_ms;
     if (!strcmp(key, "debug_gate")) return &ctx->debug_gate;
+    if (!strcmp(key, "batch_plain")) return &ctx->batch_plain;
     return nullptr;
 }
 

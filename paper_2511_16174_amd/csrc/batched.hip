@@ -5,8 +5,9 @@
 // Each matrix runs the full two-stage pipeline of evd_dsyevd.  Matrices are
 // ordered by decreasing n^3 and assigned greedily (longest processing time
 // first) to several internal streams, each with its own slice of the
-// workspace; the whole fork/join sequence is captured once into a hipGraph
-// and replayed while the batch description (sizes and pointers) is unchanged.
+// workspace; optionally ("batch_graph" = 1) the whole fork/join sequence is
+// captured once into a hipGraph and replayed while the batch description
+// (sizes and pointers) is unchanged.
 // Persistent kernels (panel QR, bulge chasing) launched from concurrent
 // streams are capped at (compute units / streams) workgroups each, so that all
 // of them fit on the chip at once whatever the interleaving.
@@ -33,7 +34,7 @@ struct BatchPlan {
 
 int num_streams(const evd_ctx_s *ctx)
 {
-    int ns = (int)(ctx->batch_streams > 0 ? ctx->batch_streams : 4);
+    int ns = (int)(ctx->batch_streams > 0 ? ctx->batch_streams : 8);
     return ns > 16 ? 16 : ns;
 }
 
@@ -161,6 +162,20 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
         ctx->panel_wgs = (saved_pw > 0 && saved_pw < cap) ? saved_pw : 0;
         ctx->timing = 0;
         ctx->in_batch = 1;
+        // "batch_plain": the persistent kernels (panel QR, bulge chasing)
+        // launched plainly rather than cooperatively, so that the streams'
+        // pipelines run side by side.  Co-residency still holds: each stream
+        // has at most one persistent kernel in flight, of at most cap
+        // workgroups, each workgroup fits on an empty compute unit, and
+        // workgroups go round-robin to the XCDs, so the at most num_cus
+        // persistent workgroups leave a compute unit without one on every XCD
+        // as long as one of them is still waiting to start; every other kernel
+        // finishes on its own.  The waits stay bounded in any case.
+        int64_t nmax = 0;
+        for (int i = 0; i < batch; ++i) nmax = n[i] > nmax ? n[i] : nmax;
+        const bool plain = ctx->batch_plain && nmax <= 512 * cap;  // panels of at most cap workgroups
+        ctx->plain_panels = plain ? 1 : 0;
+        ctx->plain_bc = plain ? 1 : 0;
         evd_status_t st = EVD_OK;
         st = evd_hip(ctx, hipEventRecord(ctx->bev[ns], origin));
         for (int k = 0; st == EVD_OK && k < ns; ++k) st = evd_hip(ctx, hipStreamWaitEvent(ctx->bstreams[k], ctx->bev[ns], 0));
@@ -182,6 +197,8 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
         ctx->panel_wgs = saved_pw;
         ctx->timing = saved_t;
         ctx->in_batch = 0;
+        ctx->plain_panels = 0;
+        ctx->plain_bc = 0;
         return st;
     };
 

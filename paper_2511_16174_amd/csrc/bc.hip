@@ -331,9 +331,11 @@ evd_status_t bc_launch(evd_ctx_t ctx, int64_t n, T *AB, int64_t ldab, T *V, T *T
     if (P < 1) P = 1;
     uint64_t limit = evd_spin_ticks(ctx);
     void *args[] = {(void *)&n, &AB, (void *)&ldab, &V, &TAU, &prog, &store_v, (void *)&front, &err, &limit};
-    hipError_t e = bs ? hipLaunchKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args, 0, bs)
-                      : hipLaunchCooperativeKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args,
-                                                   0, ctx->stream);
+    hipError_t e = bs             ? hipLaunchKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args, 0, bs)
+                   : ctx->plain_bc ? hipLaunchKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT), args, 0,
+                                                     ctx->stream)
+                                   : hipLaunchCooperativeKernel((const void *)bc_kernel<B, T>, dim3((unsigned)P), dim3(NT),
+                                                                args, 0, ctx->stream);
     return evd_hip(ctx, e);
 }
 

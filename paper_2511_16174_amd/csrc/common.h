@@ -203,6 +203,8 @@ struct evd_ctx_s {
     int64_t spin_limit_ms;    // longest inter-workgroup wait before EVD_ERR_TIMEOUT (0 = 30000)
     int64_t debug_gate;       // 1 = bulge chasing waits on a band frontier that is never published
     int plain_panels;         // internal: panel QR without a cooperative launch (while BC runs beside SBR)
+    int plain_bc;             // internal: bulge chasing without a cooperative launch (batched streams)
+    int64_t batch_plain;      // 1 = the batched driver's persistent kernels use plain launches (see batched.hip)
 };
 
 // Wall-clock ticks (100 MHz) a workgroup may wait for another one.

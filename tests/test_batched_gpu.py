@@ -16,10 +16,11 @@ def make_batch(count, seed, lmin, lmax):
     return Ls, mats
 
 
-def run_batched(ctx, mats, graph=1, streams=4, reps=1):
+def run_batched(ctx, mats, graph=1, streams=4, reps=1, plain=1):
     import torch
     ctx.set_param("batch_graph", graph)
     ctx.set_param("batch_streams", streams)
+    ctx.set_param("batch_plain", plain)
     ns = [m.shape[0] for m in mats]
     pristine = [torch.from_numpy(np.ascontiguousarray(m.T)).cuda() for m in mats]  # column-major
     As = [p.clone() for p in pristine]
@@ -43,7 +44,8 @@ def run_batched(ctx, mats, graph=1, streams=4, reps=1):
         outs.append(([w[:n].cpu().numpy() for w, n in zip(Ws, ns)],
                      [a.cpu().numpy().T.copy() for a in As], info.cpu().numpy().copy(),
                      stamps.cpu().numpy().copy(), ctx.get_param("last_graph_used")))
-    ctx.set_param("batch_graph", 1)
+    ctx.set_param("batch_graph", 0)
+    ctx.set_param("batch_plain", 1)
     return outs
 
 
@@ -142,7 +144,8 @@ def test_batched_bj_c5_full_batch():
     from tests.gpu_helpers import device_ratios
     ctx = evd.context(0)
     Ls, mats = make_batch(256, seed=7, lmin=8, lmax=45)
-    ws, Qs, info, stamps, used = run_batched(ctx, mats, graph=1, reps=1)[0]
+    ws, Qs, info, stamps, used = run_batched(ctx, mats, graph=0, streams=8, reps=1)[0]
+    ctx.set_param("batch_streams", 0)
     assert np.all(info == 0)
     worst_res = worst_orth = 0.0
     for A, w, Q in zip(mats, ws, Qs):
@@ -157,3 +160,23 @@ def test_batched_bj_c5_full_batch():
         assert M.eig_error(ws[i], oracle.syev(mats[i], jobz="N")) <= 1e-12, (i, mats[i].shape[0])
     st = stamps.reshape(-1, 2)
     assert np.all(st[:, 1] >= st[:, 0]) and np.all(st[:, 0] > 0)
+
+
+def test_batched_plain_launches_match_cooperative():
+    """The persistent kernels launched plainly (streams side by side, the
+    default) give bit for bit the results of cooperative launches."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    Ls, mats = make_batch(24, seed=21, lmin=6, lmax=30)
+    coop = run_batched(ctx, mats, graph=0, streams=8, reps=1, plain=0)[0]
+    plain = run_batched(ctx, mats, graph=0, streams=8, reps=1, plain=1)[0]
+    ctx.set_param("batch_streams", 0)
+    assert np.all(coop[2] == 0) and np.all(plain[2] == 0)
+    for a, b in zip(coop[0], plain[0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(coop[1], plain[1]):
+        assert np.array_equal(a, b)
+    for i in (0, len(mats) // 2, len(mats) - 1):
+        A = mats[i]
+        assert M.eig_error(plain[0][i], oracle.syev(A, jobz="N")) <= 1e-12
+        assert M.residual(A, plain[0][i], plain[1][i]) <= 10 and M.orthogonality(plain[1][i]) <= 10
