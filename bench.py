@@ -344,6 +344,8 @@ def main():
                     help="0 = reordered stages (Q_s H.. then Q_sb Q_d), 1 = conventional (Q_s (H.. Q_d))")
     ap.add_argument("--bcback-valu", type=int, default=0,
                     help="1 = reflector-by-reflector BC-back on the vector ALUs instead of the blocked MFMA kernel")
+    ap.add_argument("--bcback-sub", type=int, default=0, choices=[0, 16, 32, 64],
+                    help="sweeps per BC-back block reflector inside a 64-sweep group (0 = library default, 32)")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed", "batched"])
     ap.add_argument("--batch-streams", type=int, default=8, help="internal streams of the batched driver")
     ap.add_argument("--batch-graph", type=int, default=0, help="1 = replay the batch as one captured hipGraph")
@@ -393,6 +395,7 @@ def main():
     ctx.set_param("timing", 1)
     ctx.set_param("order", args.order)
     ctx.set_param("bcback_valu", args.bcback_valu)
+    ctx.set_param("bcback_sub", args.bcback_sub)
 
     lam_known = None
     if args.matrix == "known-uniform":

@@ -81,6 +81,9 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *                  the matrix cores (b = 16, 32, 64)
  *   "bcback_group" sweeps per group of the blocked BC-back: 0 = automatic
  *                  (64 for b = 64, else 32), 32 = always 32
+ *   "bcback_sub"   sweeps per block reflector inside a 64-sweep BC-back group,
+ *                  applied one after another: 16, 32 (0 = default, 32) or 64
+ *                  (one block reflector per group)
  *   "bcback_rows"  rows of Q per workgroup of the 64-sweep BC-back: 64 or 128
  *                  for all rows; 0 = automatic (128 for whole rounds of one
  *                  workgroup per compute unit, a remainder of at most one

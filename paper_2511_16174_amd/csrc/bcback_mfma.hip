@@ -417,7 +417,15 @@ __global__ __launch_bounds__(256) void bct_wide_kernel(int64_t n, int B, const d
     }
 }
 
-template <int B, int G, int NWV, bool REV>
+// SG > 0: the G sweeps of a group are applied as G/SG block reflectors of
+// SG consecutive sweeps, one after another (ascending sweeps; descending for
+// the reverse product), each with its own T: the diagonal SG x SG block of
+// the group's T (the forward recurrence of T restricted to the block's
+// columns), so the off-diagonal T blocks are never multiplied.  At B = 64,
+// G = 64: SG = 16 issues 176 MFMAs per 16 rows and step, SG = 32 184, the
+// whole group (SG = 0) 200, but each block reflector must wait for the
+// previous one's update of the window.
+template <int B, int G, int NWV, bool REV, int SG>
 __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows, int64_t n,
                                                                   const double *__restrict__ V,
                                                                   const double *__restrict__ Tg, int64_t nblk,
@@ -530,6 +538,76 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                     }
                 }
             }
+            if constexpr (SG > 0) {
+                constexpr int ST = SG / 16;   // reflector tiles per block reflector
+                if (more) fetch_group(blk, REV ? s + 1 : s - 1);
+#pragma unroll
+                for (int ii = 0; ii < G / SG; ++ii) {
+                    const int i = REV ? G / SG - 1 - ii : ii;
+                    const int j0 = i * ST;   // first reflector tile of the block
+                    // P = Q_w Y_i: tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3
+                    // (one tile: two accumulators, so consecutive products are independent)
+                    double4_t pa[ST], pb[ST];
+#pragma unroll
+                    for (int u = 0; u < ST; ++u) pa[u] = pb[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int kk = 4 * j0; kk < 4 * (j0 + ST - 1) + SHK + 4; ++kk) {
+#pragma unroll
+                        for (int u = 0; u < ST; ++u) {
+                            const int jt = j0 + u;
+                            if (kk >= 4 * jt && kk < 4 * jt + SHK + 4) {
+                                if (ST == 1 && (kk & 1))
+                                    pb[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 4 * kk + lk, 16 * jt + li), x[kk],
+                                                                                 pb[u], 0, 0, 0);
+                                else
+                                    pa[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 4 * kk + lk, 16 * jt + li), x[kk],
+                                                                                 pa[u], 0, 0, 0);
+                            }
+                        }
+                    }
+                    double4_t p1[ST];
+#pragma unroll
+                    for (int u = 0; u < ST; ++u) p1[u] = pa[u] + pb[u];
+                    // P M_i, M_i the diagonal block of -T (upper) or -T^T (lower)
+                    double4_t qa[ST], qb[ST];
+#pragma unroll
+                    for (int u = 0; u < ST; ++u) qa[u] = qb[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int kk = 4 * j0; kk < 4 * (j0 + ST); ++kk) {
+#pragma unroll
+                        for (int u = 0; u < ST; ++u) {
+                            const int jt = j0 + u;
+                            const bool nz = REV ? (kk >= 4 * jt) : (kk <= 4 * jt + 3);
+                            if (nz) {
+                                const double m = Ts[buf][wide_tile<G, REV>(jt, kk) * 64 + lane];
+                                if (ST == 1 && (kk & 1))
+                                    qb[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, p1[kk / 4 - j0][kk % 4], qb[u], 0, 0, 0);
+                                else
+                                    qa[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, p1[kk / 4 - j0][kk % 4], qa[u], 0, 0, 0);
+                            }
+                        }
+                    }
+                    double4_t p2[ST];
+#pragma unroll
+                    for (int u = 0; u < ST; ++u) p2[u] = qa[u] + qb[u];
+                    // Q_w += (P M_i) Y_i^T: window tile t meets reflectors 16 t - (B - 1) .. 16 t + 15
+#pragma unroll
+                    for (int kk = 4 * j0; kk < 4 * (j0 + ST); ++kk) {
+#pragma unroll
+                        for (int t = j0; t < j0 + ST + B / 16; ++t) {
+                            if (4 * kk + 3 >= 16 * t - (B - 1) && 4 * kk <= 16 * t + 15) {
+                                double4_t a = (double4_t){x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]};
+                                a = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 16 * t + li, 4 * kk + lk),
+                                                                         p2[kk / 4 - j0][kk % 4], a, 0, 0, 0);
+                                x[4 * t] = a[0];
+                                x[4 * t + 1] = a[1];
+                                x[4 * t + 2] = a[2];
+                                x[4 * t + 3] = a[3];
+                            }
+                        }
+                    }
+                }
+            } else {
             // P = Q_w Y: reflector tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3
             double4_t P[JT];
 #pragma unroll
@@ -580,6 +658,7 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                 x[4 * t + 2] = acc[t][2];
                 x[4 * t + 3] = acc[t][3];
             }
+            }  // SG == 0
             if (more) {
                 store_group(buf ^ 1);
                 if (REV) {
@@ -698,20 +777,31 @@ evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t 
     if (g == BC_GW) {
         // rows r0 .. r0 + rows - 1 with 128-row (two wavefronts per SIMD) or
         // 64-row workgroups, one workgroup per compute unit at a time
+        // block reflectors of 32 sweeps by default (measured at n = 32768:
+        // 1722 ms against 1776 ms for whole 64-sweep groups and 1859 ms for
+        // 16-sweep blocks)
+        const int sub = ctx->bcback_sub == 0 ? 32 : (int)ctx->bcback_sub;
         auto launch = [&](bool w8, int64_t r0, int64_t rows) {
             const dim3 grid((unsigned)evd_ceil_div(rows, w8 ? 128 : 64));
             double *Qr = Q + r0;
+#define EVD_BCW(NW, RV, SB)                                                                                          \
+    hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, NW, RV, SB>), grid, dim3(NW * 64), 0, s, rows, n, V, Tg, nblk, \
+                       Qr, ldq)
+#define EVD_BCW_SUB(NW, RV)                                                                                          \
+    do {                                                                                                             \
+        if (sub == 16) EVD_BCW(NW, RV, 16);                                                                          \
+        else if (sub == 32) EVD_BCW(NW, RV, 32);                                                                     \
+        else EVD_BCW(NW, RV, 0);                                                                                     \
+    } while (0)
             if (w8) {
-                if (rev) hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 8, true>), grid, dim3(512), 0, s, rows, n, V,
-                                            Tg, nblk, Qr, ldq);
-                else hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 8, false>), grid, dim3(512), 0, s, rows, n, V,
-                                        Tg, nblk, Qr, ldq);
+                if (rev) EVD_BCW_SUB(8, true);
+                else EVD_BCW_SUB(8, false);
             } else {
-                if (rev) hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 4, true>), grid, dim3(256), 0, s, rows, n, V,
-                                            Tg, nblk, Qr, ldq);
-                else hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 4, false>), grid, dim3(256), 0, s, rows, n, V,
-                                        Tg, nblk, Qr, ldq);
+                if (rev) EVD_BCW_SUB(4, true);
+                else EVD_BCW_SUB(4, false);
             }
+#undef EVD_BCW_SUB
+#undef EVD_BCW
         };
         if (ctx->bcback_rows) {
             launch(ctx->bcback_rows == 128, 0, mrows);

@@ -86,11 +86,12 @@ def test_bcback_blocked_matches_valu_kernel(n, b, mrows):
 
 
 @pytest.mark.parametrize("trans", ["N", "T"])
-@pytest.mark.parametrize("group,rows", [(32, 0), (64, 64), (64, 128)])
-def test_bcback_b64_group_and_row_variants(trans, group, rows):
-    """b = 64: 32- and 64-sweep groups, 64- and 128-row workgroups, on a size
-    with a ragged last group (n - 2 not a multiple of 64) and partial
-    workgroups (m_rows not a multiple of 128)."""
+@pytest.mark.parametrize("group,rows,sub", [(32, 0, 0), (64, 64, 0), (64, 128, 0), (64, 64, 16), (64, 128, 32), (64, 128, 64)])
+def test_bcback_b64_group_and_row_variants(trans, group, rows, sub):
+    """b = 64: 32- and 64-sweep groups, 64- and 128-row workgroups, 64-sweep
+    groups applied whole or as four 16-sweep block reflectors ("bcback_sub"),
+    on a size with a ragged last group (n - 2 not a multiple of 64) and
+    partial workgroups (m_rows not a multiple of 128)."""
     from paper_2511_16174_amd import evd
     import torch
     ctx = evd.context(0)
@@ -106,12 +107,14 @@ def test_bcback_b64_group_and_row_variants(trans, group, rows):
     wb = ctx.evd_dbcback_work_size(n, b)
     ctx.set_param("bcback_group", group)
     ctx.set_param("bcback_rows", rows)
+    ctx.set_param("bcback_sub", sub)
     try:
         ctx.evd_dbcback(trans, mrows, n, b, dV, dT, dX, mrows, work_dev(wb), wb)
         torch.cuda.synchronize()
     finally:
         ctx.set_param("bcback_group", 0)
         ctx.set_param("bcback_rows", 0)
+        ctx.set_param("bcback_sub", 0)
     out = from_dev(dX, mrows, n)
     assert np.max(np.abs(out - ref)) <= 100 * n * M.EPS * np.abs(X).max()
 
