@@ -346,6 +346,8 @@ def main():
                     help="1 = reflector-by-reflector BC-back on the vector ALUs instead of the blocked MFMA kernel")
     ap.add_argument("--bcback-sub", type=int, default=0, choices=[0, 16, 32, 64],
                     help="sweeps per BC-back block reflector inside a 64-sweep group (0 = library default, 32)")
+    ap.add_argument("--dc-host", type=int, default=0,
+                    help="1 = D&C on the host CPU beside the GPU back transformation (use with --order 0)")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed", "batched"])
     ap.add_argument("--batch-streams", type=int, default=8, help="internal streams of the batched driver")
     ap.add_argument("--batch-graph", type=int, default=0, help="1 = replay the batch as one captured hipGraph")
@@ -396,6 +398,7 @@ def main():
     ctx.set_param("order", args.order)
     ctx.set_param("bcback_valu", args.bcback_valu)
     ctx.set_param("bcback_sub", args.bcback_sub)
+    ctx.set_param("dc_host", args.dc_host)
 
     lam_known = None
     if args.matrix == "known-uniform":
@@ -438,7 +441,9 @@ def main():
 
     flops3 = 4.0 * n ** 3 / 3.0
     value = flops3 / t / 1e12
-    if args.order == 0:
+    if args.dc_host and args.jobz.upper() == "V":
+        names = ["sbr", "bc", "dc_host_cpu", "sbr_back", "bc_back", "wait_copy_final_gemm", "total"]
+    elif args.order == 0:
         names = ["sbr", "bc", "dc", "sbr_back", "bc_back", "final_gemm", "total"]
     else:
         names = ["sbr", "bc", "dc", "transpose", "bc_back", "sbr_back_left", "total"]
@@ -452,7 +457,7 @@ def main():
     # x 2.4 GHz).
     if args.jobz.upper() == "V":
         cand = {"bc_back": stage_ms[4]}
-        if args.order == 0:
+        if args.order == 0 and not args.dc_host:
             cand["final_gemm"] = stage_ms[5]
         kname = max(cand, key=cand.get)
         kms = cand[kname]
@@ -495,7 +500,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl,
                    "n": n, "b": b, "jobz": args.jobz, "uplo": "L", "seed": 3 if lam_known is None else args.seed,
-                   "stage_order": "reordered" if args.order == 0 else "conventional"},
+                   "stage_order": "reordered" if args.order == 0 else "conventional",
+                   "dc": "host CPU" if args.dc_host else "GPU"},
         "stage_ms": stages,
         "roofline": roofline,
     }

@@ -108,6 +108,11 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *                  progress (bulge-chasing sweeps, SBR's published band, the
  *                  panel-QR records) before the call gives up with
  *                  EVD_ERR_TIMEOUT in `info` and NaN outputs (0 = 30000)
+ *   "dc_host"      1 = with vectors, D&C runs on the host CPU in a thread
+ *                  (evd_dstedc_host) while the GPU forms Q_s H_1 ... H_m, as
+ *                  in the paper's Algorithm 1; then Q = (Q_s H_1 ... H_m) Q_d
+ *                  on the GPU.  The call then synchronises with its stream.
+ *                  "dc_host_threads": its host threads (0 = automatic).
  *   "debug_gate"   1 = bulge chasing waits for band columns that are never
  *                  published (forces EVD_ERR_TIMEOUT; for tests of that path)
  * Unknown keys return EVD_ERR_INVALID_ARG. */
@@ -309,6 +314,17 @@ evd_status_t evd_dsb2st(evd_ctx_t ctx, char jobz, int64_t n, int64_t b, double *
 evd_status_t evd_dstedc_work_size(evd_ctx_t ctx, char compz, int64_t n, size_t *bytes /*[host]*/);
 evd_status_t evd_dstedc(evd_ctx_t ctx, char compz, int64_t n, const double *d, const double *e,
                         double *W, double *Z, int64_t ldz, void *work, size_t work_bytes, int32_t *info);
+
+/* The same stage on the host CPU, as the paper places it (Algorithm 1 runs
+ * D&C in a CPU thread beside the GPUs' back transformation, Section 3.3):
+ * divide and conquer with the same tear, deflation, secular solver,
+ * Gu-Eisenstat zhat and zero-block-skipping products, spread over `threads`
+ * std::thread workers (0 = OMP_NUM_THREADS, else all hardware threads).
+ * All pointers are [host]: d (n), e (n-1), W (n), Z (ldz x n, compz 'I').
+ * *info [host, optional] = 0 or EVD_ERR_NOT_CONVERGED.  No context, no
+ * device.  evd_dsyevd uses it when "dc_host" = 1. */
+evd_status_t evd_dstedc_host(char compz, int64_t n, const double *d, const double *e, double *W, double *Z,
+                             int64_t ldz, int32_t threads, int32_t *info);
 
 /* Stage 4a, SBR-back (Section 2.1.2; Algorithm 1 genW/genQ): form
  * Q_s = (I - Y_0 T_0 Y_0^T)(I - Y_1 T_1 Y_1^T) ... in Q (n x n, ldq >= n),

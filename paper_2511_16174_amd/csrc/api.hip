@@ -121,6 +121,8 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "spin_limit_ms")) return &ctx->spin_limit_ms;
     if (!strcmp(key, "debug_gate")) return &ctx->debug_gate;
     if (!strcmp(key, "batch_plain")) return &ctx->batch_plain;
+    if (!strcmp(key, "dc_host")) return &ctx->dc_host;
+    if (!strcmp(key, "dc_host_threads")) return &ctx->dc_host_threads;
     return nullptr;
 }
 

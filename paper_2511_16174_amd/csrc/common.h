@@ -206,6 +206,9 @@ struct evd_ctx_s {
     int plain_panels;         // internal: panel QR without a cooperative launch (while BC runs beside SBR)
     int plain_bc;             // internal: bulge chasing without a cooperative launch (batched streams)
     int64_t batch_plain;      // 1 = the batched driver's persistent kernels use plain launches (see batched.hip)
+    int64_t dc_host;          // 1 = D&C on the host CPU beside the GPU back transformation (vectors)
+    int64_t dc_host_threads;  // host threads of that D&C (0 = OMP_NUM_THREADS, else all)
+    int32_t host_status;      // internal: status of the last host D&C (source of an async copy)
 };
 
 // Wall-clock ticks (100 MHz) a workgroup may wait for another one.

@@ -11,6 +11,10 @@
 // the conventional order Q = Q_s (H_1 ... H_m Q_d), which needs no final GEMM
 // (fewer flops when the stages run one after the other on one device).
 // Eigenvalues only: SBR -> BC (no reflectors kept) -> bisection.
+#include <chrono>
+#include <thread>
+#include <vector>
+
 #include "common.h"
 
 size_t dc_work_bytes(char compz, int64_t n);
@@ -26,6 +30,8 @@ evd_status_t bcback_run_rev(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, 
 evd_status_t ormsb_run(evd_ctx_t ctx, int64_t n, int64_t b, const double *A, int64_t lda, const double *T, double *C,
                        int64_t ldc, void *work);
 evd_status_t transpose_run(hipStream_t s, int64_t n, const double *A, int64_t lda, double *B, int64_t ldb);
+int host_dc_run(char compz, int64_t n, const double *d, const double *e, double *W, double *Z, int64_t ldz,
+                int threads, int maxit);
 evd_status_t nonfinite_begin(hipStream_t s, int64_t n, double *A, int64_t lda, char uplo, int *flag);
 evd_status_t nonfinite_end(hipStream_t s, int64_t n, const int *flag, double *W, double *A, int64_t lda, bool vec,
                            int32_t *info);
@@ -206,6 +212,67 @@ evd_status_t evd_dsyevd(evd_ctx_t ctx, char jobz, char uplo, int64_t n, double *
         EVD_CHECK(dc_run(ctx, 'N', n, w.d, w.e, W, nullptr, 1, w.dc, info));
         mark(3);
     } else {
+        if (ctx->dc_host && !ctx->in_batch) {
+            // the paper's placement (Algorithm 1, Section 3.3): D&C in a host
+            // thread on the tridiagonal copied to host memory, while the GPU
+            // forms Q_sb = Q_s H_1 ... H_m (reordered stages, independent of
+            // D&C); then Q_d is copied to the device and Q = Q_sb Q_d.
+            // Stage times: [2] host D&C (host clock, beside [3] and [4]),
+            // [3] SBR-back, [4] BC-back, [5] wait for the host, copy of Q_d
+            // and W, final GEMM.
+            const size_t nn = (size_t)n;
+            std::vector<double> hd(nn), he(nn), hw(nn), hz(nn * nn);
+            if (!ctx->astream) return EVD_ERR_HIP;
+            EVD_CHECK(evd_hip(ctx, hipEventRecord(ctx->ev[12], s)));
+            EVD_CHECK(evd_hip(ctx, hipStreamWaitEvent(ctx->astream, ctx->ev[12], 0)));
+            EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(hd.data(), w.d, nn * 8, hipMemcpyDeviceToHost, ctx->astream)));
+            EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(he.data(), w.e, (nn - 1) * 8, hipMemcpyDeviceToHost, ctx->astream)));
+            EVD_CHECK(evd_hip(ctx, hipEventRecord(ctx->ev[13], ctx->astream)));
+            int hst = 0;
+            float host_ms = 0.0f;
+            hipError_t herr = hipSuccess;
+            const int maxit = (ctx->dc_max_iter > 0 && ctx->dc_max_iter < 200) ? (int)ctx->dc_max_iter : 200;
+            std::thread worker([&] {
+                herr = hipEventSynchronize(ctx->ev[13]);
+                if (herr != hipSuccess) return;
+                const auto t0 = std::chrono::steady_clock::now();
+                hst = host_dc_run('I', n, hd.data(), he.data(), hw.data(), hz.data(), n, (int)ctx->dc_host_threads,
+                                  maxit);
+                host_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            });
+            evd_status_t st = orgsb_run(ctx, n, b, A, lda, w.T, w.Qs, n, w.orgsb);
+            mark(3);
+            const bool blocked = w.Tg && ctx->bcback_valu == 0 && bcback_mfma_fits(n);
+            if (st == EVD_OK && blocked) st = bcback_mfma_prepare(ctx, n, b, w.V, w.TAU, w.Tg, false);
+            if (st == EVD_OK)
+                st = blocked ? bcback_mfma_apply(ctx, n, n, b, w.V, w.Qs, n, w.Tg, false)
+                             : bcback_run(ctx, n, n, b, w.V, w.TAU, w.Qs, n);
+            mark(4);
+            worker.join();
+            EVD_CHECK(st);
+            EVD_CHECK(evd_hip(ctx, herr));
+            ctx->host_status = hst;
+            EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(w.Qd, hz.data(), nn * nn * 8, hipMemcpyHostToDevice, s)));
+            EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(W, hw.data(), nn * 8, hipMemcpyHostToDevice, s)));
+            if (info) EVD_CHECK(evd_hip(ctx, hipMemcpyAsync(info, &ctx->host_status, 4, hipMemcpyHostToDevice, s)));
+            EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, w.Qs, n, w.Qd, n, 0.0, A, lda, nullptr, 0));
+            // the host buffers stay alive until the copies have completed
+            EVD_CHECK(evd_hip(ctx, hipStreamSynchronize(s)));
+            mark(5);
+            EVD_CHECK(nonfinite_end(s, n, w.nflag, W, A, lda, vec, info));
+            if (timing) {
+                if (hipEventSynchronize(ctx->ev[5]) != hipSuccess) return EVD_ERR_HIP;
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stage_ms[0] = ms;
+                if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->stage_ms[1] = ms;
+                ctx->stage_ms[2] = host_ms;
+                if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) ctx->stage_ms[3] = ms;
+                if (hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]) == hipSuccess) ctx->stage_ms[4] = ms;
+                if (hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]) == hipSuccess) ctx->stage_ms[5] = ms;
+                if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]) == hipSuccess) ctx->stage_ms[6] = ms;
+            }
+            return evd_hip(ctx, hipGetLastError());
+        }
         // conventional order: the BC-back T factors need only the reflectors,
         // so they are formed on an auxiliary stream while D&C runs (not in
         // the batched driver, whose streams are captured into a graph)

@@ -71,7 +71,13 @@ evd_status_t evd_dsyevd_noalloc(evd_ctx_t ctx, char jobz, char uplo, int64_t n, 
     if (ctx->device < 0) return EVD_ERR_HIP;
     void *ptr = noalloc_ptr(ctx->device);
     if (!ptr) return EVD_ERR_HIP;
-    return evd_dsyevd(ctx, jobz, uplo, n, A, lda, W, ptr, (size_t)EVD_NOALLOC_SCRATCH_BYTES, info);
+    // the host-CPU D&C option keeps its tridiagonal and eigenvectors in host
+    // buffers it allocates: not used here
+    const int64_t saved = ctx->dc_host;
+    ctx->dc_host = 0;
+    const evd_status_t st = evd_dsyevd(ctx, jobz, uplo, n, A, lda, W, ptr, (size_t)EVD_NOALLOC_SCRATCH_BYTES, info);
+    ctx->dc_host = saved;
+    return st;
 }
 
 }  // extern "C"

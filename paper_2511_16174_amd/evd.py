@@ -63,6 +63,7 @@ PROTOTYPES = {
     "evd_dsb2st": (_st, [_vp, _c, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz]),
     "evd_dstedc_work_size": (_st, [_vp, _c, _i64, ctypes.POINTER(_sz)]),
     "evd_dstedc": (_st, [_vp, _c, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "evd_dstedc_host": (_st, [_c, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _vp]),
     "evd_dorgsb_work_size": (_st, [_vp, _i64, _i64, ctypes.POINTER(_sz)]),
     "evd_dorgsb": (_st, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _sz]),
     "evd_dbcback_work_size": (_st, [_vp, _i64, _i64, _vp]),

@@ -357,3 +357,20 @@ def test_bc_wait_timeout_reports_status(jobz):
     assert info == 0
     if jobz == "V":
         check(A, w, Q, oracle.syev(A, jobz="N"))
+
+
+@pytest.mark.parametrize("n,b", [(300, 32), (1500, 64)])
+def test_host_dc_beside_gpu_back_transform(n, b):
+    """"dc_host" = 1: D&C on the host CPU in a thread while the GPU forms
+    Q_s H_1 ... H_m, then Q = (Q_s H_1 ... H_m) Q_d: the oracle's gates, and
+    the eigenvalues agree with the GPU D&C's to 1e-12."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    A = W.gaussian_sym(n, seed=80 + n)
+    with params(ctx, dc_host=1, b=b):
+        w, Q, info = raw_dsyevd(ctx, A)
+    assert info == 0
+    check(A, w, Q, oracle.syev(A, jobz="N"))
+    with params(ctx, b=b):
+        w_gpu, _, _ = raw_dsyevd(ctx, A)
+    assert M.eig_error(w, w_gpu) <= 1e-12
