@@ -228,13 +228,18 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
                               size_t work_bytes, int32_t *info, double *achieved);
 
 /* Autotuner for the band half-width b (the paper fixes b = 32 for its
- * platform, Section 4.1; the best b depends on the GPU and on n).  Times
- * evd_dsyevd on A (n x n, lower triangle, not modified) for b in
- * {16, 32, 64} (two calls each, the second timed with events on the stream;
- * this call synchronises) and records the fastest b for n's size bucket
- * floor(log2 n) in the context, where evd_dsyevd, evd_dsyevd_mixed and the
- * work-size queries use it while the "b" parameter is 0.
- * [host] best_b, best_ms may be NULL. */
+ * platform, Section 4.1; the best b depends on the GPU and on n) and the
+ * blocking of the kernels around it.  Times evd_dsyevd on A (n x n, lower
+ * triangle, not modified) for the configurations (b, SBR outer block
+ * "sbr_nb", BC-back block width "bcback_sub") in
+ *   (16, 256), (16, 512), (32, 256), (32, 512),
+ *   (64, 256, 32), (64, 320, 32), (64, 512, 32), (64, 320, 64)
+ * (two calls each, the second timed with events on the stream; this call
+ * synchronises) and records the fastest for n's size bucket floor(log2 n) in
+ * the context, where evd_dsyevd, evd_dsyevd_mixed, the batched driver and
+ * the work-size queries use them while the parameters are 0.
+ * [host] best_b, best_ms may be NULL; the other choices are read back as the
+ * parameters "last_tuned_nb" and "last_tuned_sub". */
 evd_status_t evd_autotune_work_size(evd_ctx_t ctx, char jobz, int64_t n, size_t *bytes /*[host]*/);
 evd_status_t evd_autotune(evd_ctx_t ctx, char jobz, int64_t n, const double *A, int64_t lda, void *work,
                           size_t work_bytes, int64_t *best_b, float *best_ms);

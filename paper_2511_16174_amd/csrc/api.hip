@@ -122,6 +122,8 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "debug_gate")) return &ctx->debug_gate;
     if (!strcmp(key, "batch_plain")) return &ctx->batch_plain;
     if (!strcmp(key, "dc_host")) return &ctx->dc_host;
+    if (!strcmp(key, "last_tuned_nb")) return &ctx->last_tuned_nb;
+    if (!strcmp(key, "last_tuned_sub")) return &ctx->last_tuned_sub;
     if (!strcmp(key, "dc_host_threads")) return &ctx->dc_host_threads;
     return nullptr;
 }

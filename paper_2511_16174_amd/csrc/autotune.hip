@@ -1,7 +1,9 @@
-// Band-width autotuner: times evd_dsyevd for each candidate half-bandwidth b
-// on the caller's matrix (restored from A before every trial) with events on
-// the context's stream, and records the fastest b for the size bucket
-// floor(log2 n) in the context; later calls with the "b" parameter at 0 use it.
+// Autotuner: times evd_dsyevd for each candidate configuration -- half
+// bandwidth b, SBR outer block (the double-blocking width of the trailing
+// update) and, at b = 64, the BC-back block-reflector width -- on the
+// caller's matrix (restored from A before every trial) with events on the
+// context's stream, and records the fastest for the size bucket
+// floor(log2 n) in the context; later calls with those parameters at 0 use it.
 #include "common.h"
 
 namespace {
@@ -14,6 +16,12 @@ __global__ void at_copy_kernel(int64_t n, const double *A, int64_t lda, double *
     }
 }
 const int64_t kCandidates[] = {16, 32, 64};
+struct Config {
+    int64_t b, nb, sub;
+};
+// SBR outer blocks of 4 to 16 panels; at b = 64 both BC-back block widths
+const Config kConfigs[] = {{16, 256, 0}, {16, 512, 0}, {32, 256, 0}, {32, 512, 0}, {64, 256, 32}, {64, 320, 32},
+                           {64, 512, 32}, {64, 320, 64}};
 }  // namespace
 
 extern "C" {
@@ -24,7 +32,7 @@ evd_status_t evd_autotune_work_size(evd_ctx_t ctx, char jobz, int64_t n, size_t 
     if (n < 0) { ctx->last_invalid_arg = 3; return EVD_ERR_INVALID_ARG; }
     const int64_t saved = ctx->b;
     size_t best = 0;
-    for (int64_t b : kCandidates) {
+    for (int64_t b : kCandidates) {   // the workspace does not depend on the outer block or BC-back width
         ctx->b = b;
         size_t w = 0;
         evd_status_t st = evd_dsyevd_work_size(ctx, jobz, 'L', n, n > 1 ? n : 1, &w);
@@ -60,37 +68,46 @@ evd_status_t evd_autotune(evd_ctx_t ctx, char jobz, int64_t n, const double *A, 
     int32_t *info = (int32_t *)((char *)W + evd_align256((size_t)n * sizeof(double)));
     void *ework = (char *)info + 256;
     const size_t ebytes = work_bytes - (size_t)((char *)ework - base);
-    const int64_t saved_b = ctx->b, saved_t = ctx->timing;
+    const int64_t saved_b = ctx->b, saved_t = ctx->timing, saved_nb = ctx->sbr_nb, saved_sub = ctx->bcback_sub;
+    auto restore = [&] {
+        ctx->b = saved_b;
+        ctx->timing = saved_t;
+        ctx->sbr_nb = saved_nb;
+        ctx->bcback_sub = saved_sub;
+    };
     ctx->timing = 0;
     hipStream_t s = ctx->stream;
     float best = 3.4e38f;
-    int64_t bestb = 0;
-    for (int64_t b : kCandidates) {
-        if (b >= n) continue;
-        ctx->b = b;
+    Config bestc{0, 0, 0};
+    for (const Config &c : kConfigs) {
+        if (c.b >= n) continue;
+        ctx->b = c.b;
+        ctx->sbr_nb = c.nb;
+        ctx->bcback_sub = c.sub;
         float ms = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {  // first call warms up
             hipLaunchKernelGGL(at_copy_kernel, dim3(2048), dim3(256), 0, s, n, A, lda, Acopy);
-            if (hipEventRecord(ctx->ev[14], s) != hipSuccess) { ctx->b = saved_b; ctx->timing = saved_t; return EVD_ERR_HIP; }
+            if (hipEventRecord(ctx->ev[14], s) != hipSuccess) { restore(); return EVD_ERR_HIP; }
             evd_status_t st = evd_dsyevd(ctx, jobz, 'L', n, Acopy, n, W, ework, ebytes, info);
-            if (st != EVD_OK) { ctx->b = saved_b; ctx->timing = saved_t; return st; }
+            if (st != EVD_OK) { restore(); return st; }
             if (hipEventRecord(ctx->ev[15], s) != hipSuccess || hipEventSynchronize(ctx->ev[15]) != hipSuccess) {
-                ctx->b = saved_b;
-                ctx->timing = saved_t;
+                restore();
                 return EVD_ERR_HIP;
             }
             (void)hipEventElapsedTime(&ms, ctx->ev[14], ctx->ev[15]);
         }
-        if (ms < best) { best = ms; bestb = b; }
+        if (ms < best) { best = ms; bestc = c; }
     }
-    ctx->b = saved_b;
-    ctx->timing = saved_t;
-    if (bestb > 0) {
-        int bucket = 0;
-        while (bucket < 63 && ((int64_t)1 << (bucket + 1)) <= n) ++bucket;
-        ctx->tuned_b[bucket] = bestb;
+    restore();
+    if (bestc.b > 0) {
+        const int bucket = evd_size_bucket(n);
+        ctx->tuned_b[bucket] = bestc.b;
+        ctx->tuned_nb[bucket] = bestc.nb;
+        ctx->tuned_sub[bucket] = bestc.sub;
     }
-    if (best_b) *best_b = bestb;
+    ctx->last_tuned_nb = bestc.nb;
+    ctx->last_tuned_sub = bestc.sub;
+    if (best_b) *best_b = bestc.b;
     if (best_ms) *best_ms = best;
     return EVD_OK;
 }

@@ -780,7 +780,7 @@ evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t 
         // block reflectors of 32 sweeps by default (measured at n = 32768:
         // 1722 ms against 1776 ms for whole 64-sweep groups and 1859 ms for
         // 16-sweep blocks)
-        const int sub = ctx->bcback_sub == 0 ? 32 : (int)ctx->bcback_sub;
+        const int sub = evd_choose_sub(ctx, n);
         auto launch = [&](bool w8, int64_t r0, int64_t rows) {
             const dim3 grid((unsigned)evd_ceil_div(rows, w8 ? 128 : 64));
             double *Qr = Q + r0;

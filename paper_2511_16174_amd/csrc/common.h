@@ -180,6 +180,10 @@ struct evd_ctx_s {
     float stage_ms[8];
     // autotuned band width per size bucket (bucket = floor(log2 n)), 0 = none
     int64_t tuned_b[64];
+    int64_t tuned_nb[64];     // autotuned SBR outer block per size bucket (0 = none)
+    int64_t tuned_sub[64];    // autotuned BC-back block reflector per size bucket (0 = none)
+    int64_t last_tuned_nb;    // choices of the last evd_autotune call (read only)
+    int64_t last_tuned_sub;
     int64_t panel_wgs;        // panel-QR rows spread over about this many workgroups (0 = fewest)
     int64_t sbr_nb;           // SBR outer block in columns (0 = 320; <= b: single blocking)
     int64_t orgsb_nb;         // SBR-back reflector group in columns (0 = 512)
@@ -255,6 +259,27 @@ inline int64_t evd_choose_b(const evd_ctx_s *ctx, int64_t n)
     while (b > 1 && b >= n) b >>= 1;
     if (b < 1) b = 1;
     return b;
+}
+
+inline int evd_size_bucket(int64_t n)
+{
+    int bucket = 0;
+    while (bucket < 63 && ((int64_t)1 << (bucket + 1)) <= n) ++bucket;
+    return bucket;
+}
+// SBR outer block in columns: the parameter, else the autotuned value, else 0
+// (the driver's default)
+inline int64_t evd_choose_nb(const evd_ctx_s *ctx, int64_t n)
+{
+    if (ctx->sbr_nb > 0) return ctx->sbr_nb;
+    return n > 1 ? ctx->tuned_nb[evd_size_bucket(n)] : 0;
+}
+// sweeps per BC-back block reflector inside a 64-sweep group
+inline int evd_choose_sub(const evd_ctx_s *ctx, int64_t n)
+{
+    if (ctx->bcback_sub > 0) return (int)ctx->bcback_sub;
+    const int64_t t = n > 1 ? ctx->tuned_sub[evd_size_bucket(n)] : 0;
+    return t > 0 ? (int)t : 32;
 }
 
 // ---------------------------------------------------------------- internal API

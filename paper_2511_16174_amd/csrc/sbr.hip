@@ -612,7 +612,8 @@ evd_status_t sbr_run_t(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, T *A, int
         hipLaunchKernelGGL(publish_band_kernel<T>, dim3(1), dim3(64, 4), 0, s, n, b, j0, j1, p * b, (const T *)A,
                            lda, AB, ldab, ov->front, (int)value);
     };
-    const int64_t q = (ctx->sbr_nb > 0) ? ((ctx->sbr_nb / b) > 0 ? ctx->sbr_nb / b : 1)
+    const int64_t nbk = evd_choose_nb(ctx, n);
+    const int64_t q = (nbk > 0) ? ((nbk / b) > 0 ? nbk / b : 1)
                                         : ((SBR_NB / b) > 0 ? SBR_NB / b : 1);
     const int64_t qmax = w.q < q ? w.q : q;  // the accumulators hold w.q panels
     for (int64_t K0 = 0; K0 < p; K0 += qmax) {

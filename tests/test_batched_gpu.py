@@ -106,6 +106,9 @@ def test_autotune_picks_a_candidate_and_keeps_parity():
     work = torch.empty(wb // 8 + 32, dtype=torch.float64, device="cuda")
     b, ms = ctx.evd_autotune("V", n, dA, n, work, wb)
     assert b in (16, 32, 64) and ms > 0
+    nb, sub = ctx.get_param("last_tuned_nb"), ctx.get_param("last_tuned_sub")
+    assert nb in (256, 320, 512)
+    assert (sub in (32, 64)) if b == 64 else sub == 0
     w, Q = evd.eigh(dA, jobz="V")
     torch.cuda.synchronize()
     w, Q = w.cpu().numpy(), Q.cpu().numpy()
