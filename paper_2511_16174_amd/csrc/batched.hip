@@ -145,6 +145,8 @@ evd_status_t evd_dsyevd_batched(evd_ctx_t ctx, char jobz, char uplo, int32_t bat
         key = mix(key, (uint64_t)(uintptr_t)A[i]);
         key = mix(key, (uint64_t)(uintptr_t)W[i]);
         key = mix(key, (uint64_t)evd_choose_b(ctx, n[i]));
+        key = mix(key, (uint64_t)evd_choose_nb(ctx, n[i]));
+        key = mix(key, (uint64_t)evd_choose_sub(ctx, n[i]));
     }
     if (ctx->batch_graph && ctx->gexec && ctx->gkey == key) {
         ctx->last_graph_used = 1;
