@@ -346,6 +346,8 @@ def main():
                     help="1 = reflector-by-reflector BC-back on the vector ALUs instead of the blocked MFMA kernel")
     ap.add_argument("--bcback-sub", type=int, default=0, choices=[0, 16, 32, 64],
                     help="sweeps per BC-back block reflector inside a 64-sweep group (0 = library default, 32)")
+    ap.add_argument("--bcback-rt", type=int, default=0, choices=[0, 1, 2],
+                    help="16-row tiles per wavefront of the 64-sweep BC-back (0 = library default)")
     ap.add_argument("--dc-host", type=int, default=0,
                     help="1 = D&C on the host CPU beside the GPU back transformation (use with --order 0)")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed", "batched"])
@@ -398,6 +400,7 @@ def main():
     ctx.set_param("order", args.order)
     ctx.set_param("bcback_valu", args.bcback_valu)
     ctx.set_param("bcback_sub", args.bcback_sub)
+    ctx.set_param("bcback_rt", args.bcback_rt)
     ctx.set_param("dc_host", args.dc_host)
 
     lam_known = None

@@ -88,6 +88,10 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *                  for all rows; 0 = automatic (128 for whole rounds of one
  *                  workgroup per compute unit, a remainder of at most one
  *                  round of 64-row workgroups as such, else 128)
+ *   "bcback_rt"    16-row tiles per wavefront of the 128-row workgroups of
+ *                  the 64-sweep BC-back with block reflectors: 1 (eight
+ *                  wavefronts; 0 = default) or 2 (four wavefronts, each LDS
+ *                  operand feeding two row tiles)
  *   "orgsb_nb"     panels of b columns aggregated into one block reflector in
  *                  SBR-back, in columns (0 = 512)
  *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 320;

@@ -110,6 +110,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "sbr_nb")) return &ctx->sbr_nb;
     if (!strcmp(key, "bcback_valu")) return &ctx->bcback_valu;
     if (!strcmp(key, "bcback_sub")) return &ctx->bcback_sub;
+    if (!strcmp(key, "bcback_rt")) return &ctx->bcback_rt;
     if (!strcmp(key, "orgsb_nb")) return &ctx->orgsb_nb;
     if (!strcmp(key, "batch_streams")) return &ctx->batch_streams;
     if (!strcmp(key, "batch_graph")) return &ctx->batch_graph;
@@ -136,7 +137,8 @@ evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value)
     if (value < 0) { ctx->last_invalid_arg = 3; return EVD_ERR_INVALID_ARG; }
     if ((slot == &ctx->bcback_group && value != 0 && value != 32 && value != 64) ||
         (slot == &ctx->bcback_rows && value != 0 && value != 64 && value != 128) ||
-        (slot == &ctx->bcback_sub && value != 0 && value != 16 && value != 32 && value != 64)) {
+        (slot == &ctx->bcback_sub && value != 0 && value != 16 && value != 32 && value != 64) ||
+        (slot == &ctx->bcback_rt && value > 2)) {
         ctx->last_invalid_arg = 3;
         return EVD_ERR_INVALID_ARG;
     }

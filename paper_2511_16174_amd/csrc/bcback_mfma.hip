@@ -425,12 +425,19 @@ __global__ __launch_bounds__(256) void bct_wide_kernel(int64_t n, int B, const d
 // G = 64: SG = 16 issues 176 MFMAs per 16 rows and step, SG = 32 184, the
 // whole group (SG = 0) 200, but each block reflector must wait for the
 // previous one's update of the window.
-template <int B, int G, int NWV, bool REV, int SG>
+//
+// RT: tiles of 16 rows per wavefront.  With RT = 2 every LDS operand (a
+// fragment of Y or of T) feeds two MFMAs, one per row tile, and a wavefront
+// carries two independent accumulation chains, so one wavefront per SIMD
+// keeps the matrix core fed without a second wavefront to cover LDS latency
+// (and the register file of a SIMD holds the two windows of one wavefront).
+template <int B, int G, int NWV, bool REV, int SG, int RT>
 __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows, int64_t n,
                                                                   const double *__restrict__ V,
                                                                   const double *__restrict__ Tg, int64_t nblk,
                                                                   double *__restrict__ Q, int64_t ldq)
 {
+    static_assert(RT == 1 || SG > 0, "several row tiles per wavefront need block reflectors");
     constexpr int W = G + B;      // window columns
     constexpr int KW = W / 4;     // k-steps over the window
     constexpr int SHK = B / 4;    // k-steps the window slides per step
@@ -444,6 +451,7 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
     constexpr int TS = NTT * 64;
     constexpr int NTH = NWV * 64;
     constexpr int NV = G * B / NTH, NT = TS / NTH;
+    constexpr int RW = 16 * RT;   // rows per wavefront
     static_assert(W % 16 == 0 && (G * B) % NTH == 0 && TS % NTH == 0, "tile shapes");
     __shared__ double Vs[2][VS];
     __shared__ double Ts[2][TS];
@@ -452,9 +460,11 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * (16 * NWV) + wave * 16;
-    const bool rows_full = row0 + 16 <= mrows;
-    const bool rowok = row0 + li < mrows;
+    const int64_t row0 = (int64_t)blockIdx.x * (RW * NWV) + wave * RW;
+    const bool rows_full = row0 + RW <= mrows;
+    bool rowok[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) rowok[r] = row0 + 16 * r + li < mrows;
     double *Qw = Q + row0;
     const int64_t ldq4 = 4 * ldq;
     const uint32_t loff = ((uint32_t)li + (uint32_t)lk * (uint32_t)ldq) * 8u;
@@ -493,8 +503,8 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
     // Y(r, c) of the group in buffer buf: window row r, reflector c
     auto yv = [&](int buf, int r, int c) -> double { return Vs[buf][VPAD + c * LDV + (r - c)]; };
 
-    double x[KW];
-    double pre[SHK];
+    double x[RT][KW];
+    double pre[RT][SHK];
     const int64_t blk_first = REV ? nblk - 1 : 0;
     for (int64_t blk = blk_first; REV ? blk >= 0 : blk < nblk; blk += REV ? -1 : 1) {
         const int64_t c0 = blk * G;
@@ -503,15 +513,19 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
         if (S == 0) continue;
         int64_t base = REV ? c0 + 1 : c0 + 1 + (S - 1) * B;
         {
-            const double *Qc = Qw + base * ldq;
-            if (rows_full && base + W <= n) {
+            const bool wfull = rows_full && base + W <= n;
 #pragma unroll
-                for (int kk = 0; kk < KW; ++kk, Qc += ldq4) x[kk] = at(Qc, loff);
-            } else {
+            for (int r = 0; r < RT; ++r) {
+                const double *Qc = Qw + 16 * r + base * ldq;
+                if (wfull) {
 #pragma unroll
-                for (int kk = 0; kk < KW; ++kk) {
-                    const int64_t col = base + 4 * kk + lk;
-                    x[kk] = (rowok && col < n) ? at(Qc + kk * ldq4, loff) : 0.0;
+                    for (int kk = 0; kk < KW; ++kk, Qc += ldq4) x[r][kk] = at(Qc, loff);
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KW; ++kk) {
+                        const int64_t col = base + 4 * kk + lk;
+                        x[r][kk] = (rowok[r] && col < n) ? at(Qc + kk * ldq4, loff) : 0.0;
+                    }
                 }
             }
         }
@@ -526,15 +540,18 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
             const bool full = rows_full && base + W + B <= n;
             if (more) {
                 const int64_t pcol = REV ? base + W : base - B;
-                const double *Qc = Qw + pcol * ldq;
-                if (full) {
 #pragma unroll
-                    for (int k = 0; k < SHK; ++k, Qc += ldq4) pre[k] = at(Qc, loff);
-                } else {
+                for (int r = 0; r < RT; ++r) {
+                    const double *Qc = Qw + 16 * r + pcol * ldq;
+                    if (full) {
 #pragma unroll
-                    for (int k = 0; k < SHK; ++k) {
-                        const int64_t col = pcol + 4 * k + lk;
-                        pre[k] = (rowok && col < n) ? at(Qc + k * ldq4, loff) : 0.0;
+                        for (int k = 0; k < SHK; ++k, Qc += ldq4) pre[r][k] = at(Qc, loff);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < SHK; ++k) {
+                            const int64_t col = pcol + 4 * k + lk;
+                            pre[r][k] = (rowok[r] && col < n) ? at(Qc + k * ldq4, loff) : 0.0;
+                        }
                     }
                 }
             }
@@ -547,31 +564,40 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                     const int j0 = i * ST;   // first reflector tile of the block
                     // P = Q_w Y_i: tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3
                     // (one tile: two accumulators, so consecutive products are independent)
-                    double4_t pa[ST], pb[ST];
+                    double4_t pa[RT][ST], pb[RT][ST];
 #pragma unroll
-                    for (int u = 0; u < ST; ++u) pa[u] = pb[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int u = 0; u < ST; ++u) pa[r][u] = pb[r][u] = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                     for (int kk = 4 * j0; kk < 4 * (j0 + ST - 1) + SHK + 4; ++kk) {
 #pragma unroll
                         for (int u = 0; u < ST; ++u) {
                             const int jt = j0 + u;
                             if (kk >= 4 * jt && kk < 4 * jt + SHK + 4) {
-                                if (ST == 1 && (kk & 1))
-                                    pb[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 4 * kk + lk, 16 * jt + li), x[kk],
-                                                                                 pb[u], 0, 0, 0);
-                                else
-                                    pa[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 4 * kk + lk, 16 * jt + li), x[kk],
-                                                                                 pa[u], 0, 0, 0);
+                                const double ya = yv(buf, 4 * kk + lk, 16 * jt + li);
+#pragma unroll
+                                for (int r = 0; r < RT; ++r) {
+                                    if (ST == 1 && (kk & 1))
+                                        pb[r][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya, x[r][kk], pb[r][u], 0, 0, 0);
+                                    else
+                                        pa[r][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya, x[r][kk], pa[r][u], 0, 0, 0);
+                                }
                             }
                         }
                     }
-                    double4_t p1[ST];
+                    double4_t p1[RT][ST];
 #pragma unroll
-                    for (int u = 0; u < ST; ++u) p1[u] = pa[u] + pb[u];
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int u = 0; u < ST; ++u)
+                            p1[r][u] = (ST == 1) ? pa[r][u] + pb[r][u] : pa[r][u];  // pb is used only when ST == 1
                     // P M_i, M_i the diagonal block of -T (upper) or -T^T (lower)
-                    double4_t qa[ST], qb[ST];
+                    double4_t qa[RT][ST], qb[RT][ST];
 #pragma unroll
-                    for (int u = 0; u < ST; ++u) qa[u] = qb[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int u = 0; u < ST; ++u) qa[r][u] = qb[r][u] = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                     for (int kk = 4 * j0; kk < 4 * (j0 + ST); ++kk) {
 #pragma unroll
@@ -580,29 +606,39 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                             const bool nz = REV ? (kk >= 4 * jt) : (kk <= 4 * jt + 3);
                             if (nz) {
                                 const double m = Ts[buf][wide_tile<G, REV>(jt, kk) * 64 + lane];
-                                if (ST == 1 && (kk & 1))
-                                    qb[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, p1[kk / 4 - j0][kk % 4], qb[u], 0, 0, 0);
-                                else
-                                    qa[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, p1[kk / 4 - j0][kk % 4], qa[u], 0, 0, 0);
+#pragma unroll
+                                for (int r = 0; r < RT; ++r) {
+                                    if (ST == 1 && (kk & 1))
+                                        qb[r][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, p1[r][kk / 4 - j0][kk % 4],
+                                                                                        qb[r][u], 0, 0, 0);
+                                    else
+                                        qa[r][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, p1[r][kk / 4 - j0][kk % 4],
+                                                                                        qa[r][u], 0, 0, 0);
+                                }
                             }
                         }
                     }
-                    double4_t p2[ST];
+                    double4_t p2[RT][ST];
 #pragma unroll
-                    for (int u = 0; u < ST; ++u) p2[u] = qa[u] + qb[u];
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int u = 0; u < ST; ++u) p2[r][u] = (ST == 1) ? qa[r][u] + qb[r][u] : qa[r][u];
                     // Q_w += (P M_i) Y_i^T: window tile t meets reflectors 16 t - (B - 1) .. 16 t + 15
 #pragma unroll
                     for (int kk = 4 * j0; kk < 4 * (j0 + ST); ++kk) {
 #pragma unroll
                         for (int t = j0; t < j0 + ST + B / 16; ++t) {
                             if (4 * kk + 3 >= 16 * t - (B - 1) && 4 * kk <= 16 * t + 15) {
-                                double4_t a = (double4_t){x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]};
-                                a = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 16 * t + li, 4 * kk + lk),
-                                                                         p2[kk / 4 - j0][kk % 4], a, 0, 0, 0);
-                                x[4 * t] = a[0];
-                                x[4 * t + 1] = a[1];
-                                x[4 * t + 2] = a[2];
-                                x[4 * t + 3] = a[3];
+                                const double ya = yv(buf, 16 * t + li, 4 * kk + lk);
+#pragma unroll
+                                for (int r = 0; r < RT; ++r) {
+                                    double4_t a = (double4_t){x[r][4 * t], x[r][4 * t + 1], x[r][4 * t + 2], x[r][4 * t + 3]};
+                                    a = __builtin_amdgcn_mfma_f64_16x16x4f64(ya, p2[r][kk / 4 - j0][kk % 4], a, 0, 0, 0);
+                                    x[r][4 * t] = a[0];
+                                    x[r][4 * t + 1] = a[1];
+                                    x[r][4 * t + 2] = a[2];
+                                    x[r][4 * t + 3] = a[3];
+                                }
                             }
                         }
                     }
@@ -617,7 +653,7 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
 #pragma unroll
                 for (int jt = 0; jt < JT; ++jt) {
                     if (kk >= 4 * jt && kk < 4 * jt + SHK + 4)
-                        P[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 4 * kk + lk, 16 * jt + li), x[kk], P[jt],
+                        P[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv(buf, 4 * kk + lk, 16 * jt + li), x[0][kk], P[jt],
                                                                      0, 0, 0);
                 }
             }
@@ -641,7 +677,7 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
             // Q_w += P2 Y^T: window tile t meets reflectors 16 t - (B - 1) .. 16 t + 15
             double4_t acc[WT];
 #pragma unroll
-            for (int t = 0; t < WT; ++t) acc[t] = (double4_t){x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]};
+            for (int t = 0; t < WT; ++t) acc[t] = (double4_t){x[0][4 * t], x[0][4 * t + 1], x[0][4 * t + 2], x[0][4 * t + 3]};
 #pragma unroll
             for (int kk = 0; kk < GK; ++kk) {
 #pragma unroll
@@ -653,47 +689,53 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
             }
 #pragma unroll
             for (int t = 0; t < WT; ++t) {
-                x[4 * t] = acc[t][0];
-                x[4 * t + 1] = acc[t][1];
-                x[4 * t + 2] = acc[t][2];
-                x[4 * t + 3] = acc[t][3];
+                x[0][4 * t] = acc[t][0];
+                x[0][4 * t + 1] = acc[t][1];
+                x[0][4 * t + 2] = acc[t][2];
+                x[0][4 * t + 3] = acc[t][3];
             }
             }  // SG == 0
             if (more) {
                 store_group(buf ^ 1);
                 if (REV) {
-                    double *Qc = Qw + base * ldq;
-                    if (full) {
 #pragma unroll
-                        for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[kk];
-                    } else {
+                    for (int r = 0; r < RT; ++r) {
+                        double *Qc = Qw + 16 * r + base * ldq;
+                        if (full) {
 #pragma unroll
-                        for (int kk = 0; kk < SHK; ++kk) {
-                            const int64_t col = base + 4 * kk + lk;
-                            if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[kk];
+                            for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[r][kk];
+                        } else {
+#pragma unroll
+                            for (int kk = 0; kk < SHK; ++kk) {
+                                const int64_t col = base + 4 * kk + lk;
+                                if (rowok[r] && col < n) at(Qc + kk * ldq4, loff) = x[r][kk];
+                            }
                         }
+#pragma unroll
+                        for (int kk = 0; kk < KW - SHK; ++kk) x[r][kk] = x[r][kk + SHK];
+#pragma unroll
+                        for (int k = 0; k < SHK; ++k) x[r][KW - SHK + k] = pre[r][k];
                     }
-#pragma unroll
-                    for (int kk = 0; kk < KW - SHK; ++kk) x[kk] = x[kk + SHK];
-#pragma unroll
-                    for (int k = 0; k < SHK; ++k) x[KW - SHK + k] = pre[k];
                     base += B;
                 } else {
-                    double *Qc = Qw + (base + W - B) * ldq;
-                    if (full) {
 #pragma unroll
-                        for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[KW - SHK + kk];
-                    } else {
+                    for (int r = 0; r < RT; ++r) {
+                        double *Qc = Qw + 16 * r + (base + W - B) * ldq;
+                        if (full) {
 #pragma unroll
-                        for (int kk = 0; kk < SHK; ++kk) {
-                            const int64_t col = base + W - B + 4 * kk + lk;
-                            if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[KW - SHK + kk];
+                            for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[r][KW - SHK + kk];
+                        } else {
+#pragma unroll
+                            for (int kk = 0; kk < SHK; ++kk) {
+                                const int64_t col = base + W - B + 4 * kk + lk;
+                                if (rowok[r] && col < n) at(Qc + kk * ldq4, loff) = x[r][KW - SHK + kk];
+                            }
                         }
+#pragma unroll
+                        for (int kk = KW - 1; kk >= SHK; --kk) x[r][kk] = x[r][kk - SHK];
+#pragma unroll
+                        for (int k = 0; k < SHK; ++k) x[r][k] = pre[r][k];
                     }
-#pragma unroll
-                    for (int kk = KW - 1; kk >= SHK; --kk) x[kk] = x[kk - SHK];
-#pragma unroll
-                    for (int k = 0; k < SHK; ++k) x[k] = pre[k];
                     base -= B;
                 }
             }
@@ -701,15 +743,19 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
             buf ^= 1;
         }
         {
-            double *Qc = Qw + base * ldq;
-            if (rows_full && base + W <= n) {
+            const bool wfull = rows_full && base + W <= n;
 #pragma unroll
-                for (int kk = 0; kk < KW; ++kk, Qc += ldq4) at(Qc, loff) = x[kk];
-            } else {
+            for (int r = 0; r < RT; ++r) {
+                double *Qc = Qw + 16 * r + base * ldq;
+                if (wfull) {
 #pragma unroll
-                for (int kk = 0; kk < KW; ++kk) {
-                    const int64_t col = base + 4 * kk + lk;
-                    if (rowok && col < n) at(Qc + kk * ldq4, loff) = x[kk];
+                    for (int kk = 0; kk < KW; ++kk, Qc += ldq4) at(Qc, loff) = x[r][kk];
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KW; ++kk) {
+                        const int64_t col = base + 4 * kk + lk;
+                        if (rowok[r] && col < n) at(Qc + kk * ldq4, loff) = x[r][kk];
+                    }
                 }
             }
         }
@@ -781,25 +827,37 @@ evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t 
         // 1722 ms against 1776 ms for whole 64-sweep groups and 1859 ms for
         // 16-sweep blocks)
         const int sub = evd_choose_sub(ctx, n);
+        // two 16-row tiles per wavefront (4 wavefronts, 128 rows) when block
+        // reflectors are used and "bcback_rt" asks for it
+        const bool rt2 = (sub == 16 || sub == 32) && ctx->bcback_rt == 2;
         auto launch = [&](bool w8, int64_t r0, int64_t rows) {
             const dim3 grid((unsigned)evd_ceil_div(rows, w8 ? 128 : 64));
             double *Qr = Q + r0;
-#define EVD_BCW(NW, RV, SB)                                                                                          \
-    hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, NW, RV, SB>), grid, dim3(NW * 64), 0, s, rows, n, V, Tg, nblk, \
-                       Qr, ldq)
+#define EVD_BCW(NW, RV, SB, R)                                                                                      \
+    hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, NW, RV, SB, R>), grid, dim3(NW * 64), 0, s, rows, n, V, Tg,   \
+                       nblk, Qr, ldq)
 #define EVD_BCW_SUB(NW, RV)                                                                                          \
     do {                                                                                                             \
-        if (sub == 16) EVD_BCW(NW, RV, 16);                                                                          \
-        else if (sub == 32) EVD_BCW(NW, RV, 32);                                                                     \
-        else EVD_BCW(NW, RV, 0);                                                                                     \
+        if (sub == 16) EVD_BCW(NW, RV, 16, 1);                                                                       \
+        else if (sub == 32) EVD_BCW(NW, RV, 32, 1);                                                                  \
+        else EVD_BCW(NW, RV, 0, 1);                                                                                  \
     } while (0)
-            if (w8) {
+#define EVD_BCW_RT2(RV)                                                                                              \
+    do {                                                                                                             \
+        if (sub == 16) EVD_BCW(4, RV, 16, 2);                                                                        \
+        else EVD_BCW(4, RV, 32, 2);                                                                                  \
+    } while (0)
+            if (w8 && rt2) {
+                if (rev) EVD_BCW_RT2(true);
+                else EVD_BCW_RT2(false);
+            } else if (w8) {
                 if (rev) EVD_BCW_SUB(8, true);
                 else EVD_BCW_SUB(8, false);
             } else {
                 if (rev) EVD_BCW_SUB(4, true);
                 else EVD_BCW_SUB(4, false);
             }
+#undef EVD_BCW_RT2
 #undef EVD_BCW_SUB
 #undef EVD_BCW
         };

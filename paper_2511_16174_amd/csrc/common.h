@@ -189,6 +189,7 @@ struct evd_ctx_s {
     int64_t orgsb_nb;         // SBR-back reflector group in columns (0 = 512)
     int64_t bcback_valu;      // 1 = reflector-by-reflector BC-back on the vector ALUs (0 = blocked MFMA)
     int64_t bcback_sub;       // sweeps per block reflector inside a 64-sweep group (0 = 32, 16, 32, 64)
+    int64_t bcback_rt;        // 16-row tiles per wavefront of the 64-sweep BC-back (0 = 1, 1, 2)
     int64_t batch_streams;    // streams used by the batched driver (0 = 4)
     int64_t batch_graph;      // 1 = capture the batched launch sequence in a hipGraph
     int64_t last_graph_used;  // 1 if the last batched call ran from a graph

@@ -126,19 +126,19 @@ def test_conventional_stage_order(n, b):
 
 
 @pytest.mark.parametrize("order", [0, 1])
-@pytest.mark.parametrize("n,b,sub", [(300, 16, 0), (515, 32, 0), (700, 64, 0), (1100, 64, 64), (700, 64, 16),
-                                     (1100, 64, 32)])
-def test_blocked_bcback_matches_reflector_by_reflector(n, b, sub, order):
+@pytest.mark.parametrize("n,b,sub,rt", [(300, 16, 0, 0), (515, 32, 0, 0), (700, 64, 0, 0), (1100, 64, 64, 0),
+                                        (700, 64, 16, 0), (1100, 64, 32, 0), (1100, 64, 32, 2), (700, 64, 16, 2)])
+def test_blocked_bcback_matches_reflector_by_reflector(n, b, sub, rt, order):
     """The blocked BC-back on the matrix cores (groups of sweeps in compact
-    WY; at b = 64 also as 16-sweep block reflectors, "bcback_sub") and the
-    reflector-by-reflector kernel give the same eigenvectors up to rounding,
-    in both stage orders."""
+    WY; at b = 64 also as 16-sweep block reflectors, "bcback_sub", with one or
+    two 16-row tiles per wavefront, "bcback_rt") and the reflector-by-reflector
+    kernel give the same eigenvectors up to rounding, in both stage orders."""
     from paper_2511_16174_amd import evd
     ctx = evd.context(0)
     A = W.gaussian_sym(n, seed=n + b + order)
     out = []
     for valu in (0, 1):
-        with params(ctx, order=order, bcback_valu=valu, bcback_sub=sub):
+        with params(ctx, order=order, bcback_valu=valu, bcback_sub=sub, bcback_rt=rt):
             out.append(gpu_eigh(A, b=b))
     (w0, Q0), (w1, Q1) = out
     assert np.array_equal(w0, w1)
