@@ -459,6 +459,12 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // Two wavefronts share a SIMD, and the barrier at the end of every step
+    // lines them up, so their load-issue phases would coincide and leave the
+    // matrix core idle.  The upper half of the wavefronts issues its loads
+    // after the first block reflector instead of at the start of the step,
+    // while the lower half is already multiplying.
+    const bool late = SG > 0 && NWV >= 8 && (wave & (NWV / 2)) != 0;
     const int li = lane & 15, lk = lane >> 4;
     const int64_t row0 = (int64_t)blockIdx.x * (RW * NWV) + wave * RW;
     const bool rows_full = row0 + RW <= mrows;
@@ -538,26 +544,32 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
             const int64_t s = REV ? it : S - 1 - it;
             const bool more = it + 1 < S;
             const bool full = rows_full && base + W + B <= n;
-            if (more) {
-                const int64_t pcol = REV ? base + W : base - B;
+            // next window columns (pre) and next group (Y, T) into registers
+            auto issue_loads = [&]() {
+                if (more) {
+                    const int64_t pcol = REV ? base + W : base - B;
 #pragma unroll
-                for (int r = 0; r < RT; ++r) {
-                    const double *Qc = Qw + 16 * r + pcol * ldq;
-                    if (full) {
+                    for (int r = 0; r < RT; ++r) {
+                        const double *Qc = Qw + 16 * r + pcol * ldq;
+                        if (full) {
 #pragma unroll
-                        for (int k = 0; k < SHK; ++k, Qc += ldq4) pre[r][k] = at(Qc, loff);
-                    } else {
+                            for (int k = 0; k < SHK; ++k, Qc += ldq4) pre[r][k] = at(Qc, loff);
+                        } else {
 #pragma unroll
-                        for (int k = 0; k < SHK; ++k) {
-                            const int64_t col = pcol + 4 * k + lk;
-                            pre[r][k] = (rowok[r] && col < n) ? at(Qc + k * ldq4, loff) : 0.0;
+                            for (int k = 0; k < SHK; ++k) {
+                                const int64_t col = pcol + 4 * k + lk;
+                                pre[r][k] = (rowok[r] && col < n) ? at(Qc + k * ldq4, loff) : 0.0;
+                            }
                         }
                     }
                 }
-            }
+                if constexpr (SG > 0) {
+                    if (more) fetch_group(blk, REV ? s + 1 : s - 1);
+                }
+            };
+            if (!late) issue_loads();
             if constexpr (SG > 0) {
                 constexpr int ST = SG / 16;   // reflector tiles per block reflector
-                if (more) fetch_group(blk, REV ? s + 1 : s - 1);
 #pragma unroll
                 for (int ii = 0; ii < G / SG; ++ii) {
                     const int i = REV ? G / SG - 1 - ii : ii;
@@ -642,6 +654,7 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                             }
                         }
                     }
+                    if (late && ii == 0) issue_loads();
                 }
             } else {
             // P = Q_w Y: reflector tile jt meets window k-steps 4 jt .. 4 jt + B/4 + 3
