@@ -40,6 +40,25 @@ __device__ __forceinline__ const P &at(const P *base, uint32_t byte_off)
     return *(const P *)((const char *)base + byte_off);
 }
 
+// Raw buffer access to nk window k-steps (4 nk columns) starting at p, column
+// stride ldq doubles: a wave-uniform descriptor, the lane's row offset in the
+// vector offset and the k-step offset in the scalar offset, so no 64-bit
+// address is formed per access (requires nk * 4 * ldq * 8 < 2^31).
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t window_rsrc(const double *p, int nk, int64_t ldq4)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)((uint32_t)nk * (uint32_t)ldq4 * 8u),
+                                             (int)EVD_BUF_DWORD3);
+}
+__device__ __forceinline__ double window_load(__amdgpu_buffer_rsrc_t rs, uint32_t loff, int k, int64_t ldq4)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)loff, (int)(k * ldq4 * 8), 0));
+}
+__device__ __forceinline__ void window_store(__amdgpu_buffer_rsrc_t rs, uint32_t loff, int k, int64_t ldq4, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, (int)loff, (int)(k * ldq4 * 8), 0);
+}
+
 __global__ __launch_bounds__(64) void bct_kernel(int64_t n, int B, const double *__restrict__ V,
                                                  const double *__restrict__ TAU, double *__restrict__ Tg, int64_t nblk)
 {
@@ -552,8 +571,9 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                     for (int r = 0; r < RT; ++r) {
                         const double *Qc = Qw + 16 * r + pcol * ldq;
                         if (full) {
+                            const __amdgpu_buffer_rsrc_t rs = window_rsrc(Qc, SHK, ldq4);
 #pragma unroll
-                            for (int k = 0; k < SHK; ++k, Qc += ldq4) pre[r][k] = at(Qc, loff);
+                            for (int k = 0; k < SHK; ++k) pre[r][k] = window_load(rs, loff, k, ldq4);
                         } else {
 #pragma unroll
                             for (int k = 0; k < SHK; ++k) {
@@ -715,8 +735,9 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                     for (int r = 0; r < RT; ++r) {
                         double *Qc = Qw + 16 * r + base * ldq;
                         if (full) {
+                            const __amdgpu_buffer_rsrc_t rs = window_rsrc(Qc, SHK, ldq4);
 #pragma unroll
-                            for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[r][kk];
+                            for (int kk = 0; kk < SHK; ++kk) window_store(rs, loff, kk, ldq4, x[r][kk]);
                         } else {
 #pragma unroll
                             for (int kk = 0; kk < SHK; ++kk) {
@@ -735,8 +756,9 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                     for (int r = 0; r < RT; ++r) {
                         double *Qc = Qw + 16 * r + (base + W - B) * ldq;
                         if (full) {
+                            const __amdgpu_buffer_rsrc_t rs = window_rsrc(Qc, SHK, ldq4);
 #pragma unroll
-                            for (int kk = 0; kk < SHK; ++kk, Qc += ldq4) at(Qc, loff) = x[r][KW - SHK + kk];
+                            for (int kk = 0; kk < SHK; ++kk) window_store(rs, loff, kk, ldq4, x[r][KW - SHK + kk]);
                         } else {
 #pragma unroll
                             for (int kk = 0; kk < SHK; ++kk) {

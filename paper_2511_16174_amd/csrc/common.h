@@ -345,7 +345,9 @@ evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob
 // reflector groups (bcback_mfma_t_elems doubles, 0 for other b), then
 // Q <- Q H_1 ... H_m (rev false) or Q H_m ... H_1 (rev true).
 size_t bcback_mfma_t_elems(int64_t n, int64_t b);
-inline bool bcback_mfma_fits(int64_t ldq) { return ldq > 0 && ldq <= ((int64_t)1 << 27); }  // 3 ldq + 15 doubles in a 32-bit byte offset
+// the blocked kernels address 64 window columns (16 k-steps) through one
+// buffer descriptor: 64 ldq doubles in a 31-bit byte range
+inline bool bcback_mfma_fits(int64_t ldq) { return ldq > 0 && ldq < ((int64_t)1 << 22); }
 evd_status_t bcback_mfma_prepare(evd_ctx_t ctx, int64_t n, int64_t b, const double *V, const double *TAU, double *Tg,
                                  bool rev);
 evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t b, const double *V, double *Q,
