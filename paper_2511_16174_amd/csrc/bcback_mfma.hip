@@ -499,22 +499,22 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
     __syncthreads();
 
     double gv[NV], gt[NT];
+    // buffer loads over the group's vectors (G x B, the sweeps past the last
+    // one of a ragged last group fall outside the descriptor and read as zero)
+    // and its T tiles
     auto fetch_group = [&](int64_t blk, int64_t s) {
         const int64_t c0 = blk * G;
-        const double *Vg = V + (s * n + c0) * B;
-        if (c0 + G <= nsweeps) {
+        const int64_t nvalid = (c0 + G <= nsweeps) ? G : nsweeps - c0;
+        const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(V + (s * n + c0) * B), (short)0, (int)(nvalid * B * 8), (int)EVD_BUF_DWORD3);
+        const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(Tg + (s * nblk + blk) * (int64_t)TS), (short)0, (int)(TS * 8), (int)EVD_BUF_DWORD3);
 #pragma unroll
-            for (int r = 0; r < NV; ++r) gv[r] = Vg[tid + r * NTH];
-        } else {
+        for (int r = 0; r < NV; ++r)
+            gv[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rv, tid * 8, r * NTH * 8, 0));
 #pragma unroll
-            for (int r = 0; r < NV; ++r) {
-                const int e = tid + r * NTH;
-                gv[r] = (c0 + e / B < nsweeps) ? Vg[e] : 0.0;
-            }
-        }
-        const double *T = Tg + (s * nblk + blk) * (int64_t)TS;
-#pragma unroll
-        for (int r = 0; r < NT; ++r) gt[r] = T[tid + r * NTH];
+        for (int r = 0; r < NT; ++r)
+            gt[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rt, tid * 8, r * NTH * 8, 0));
     };
     auto store_group = [&](int buf) {
 #pragma unroll
