@@ -92,6 +92,10 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *                  the 64-sweep BC-back with block reflectors: 1 (eight
  *                  wavefronts; 0 = default) or 2 (four wavefronts, each LDS
  *                  operand feeding two row tiles)
+ *   "gemm_staged"  1: every FP64 product stages its K slices through registers;
+ *                  0 (default): 128 x 128 tiles with K slices of 16 that are
+ *                  all whole load them straight into LDS (same results, bit
+ *                  for bit).  Applies to every context of the process.
  *   "orgsb_nb"     panels of b columns aggregated into one block reflector in
  *                  SBR-back, in columns (0 = 512)
  *   "sbr_nb"       SBR outer (double-blocking) block in columns, 0 = 320;
@@ -141,7 +145,9 @@ evd_status_t evd_get_stage_times(evd_ctx_t ctx, float *ms);
  *        'S' op(A) = the symmetric m x m matrix whose lower triangle is stored
  *            in A (k must equal m; the strict upper triangle is not read).
  *   opb: 'N' op(B) = B (k x n), 'T' op(B) = B^T (B is n x k).
- *   lower_c: nonzero -> only entries C(i, j) with i >= j are written (SYR2K-style).
+ *   lower_c: nonzero -> only entries C(i, j) with i >= j are written (SYR2K-style);
+ *            2 -> each of them is also stored at C(j, i) (square C, opa 'N',
+ *            opb 'T'; the symmetric rank-k update that keeps both triangles).
  * `work` (may be NULL) is scratch for split-K partial sums; when it is NULL or
  * smaller than evd_dgemm_work_size() the product runs without K splitting. */
 evd_status_t evd_dgemm(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_t m, int64_t n, int64_t k,

@@ -111,6 +111,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "bcback_valu")) return &ctx->bcback_valu;
     if (!strcmp(key, "bcback_sub")) return &ctx->bcback_sub;
     if (!strcmp(key, "bcback_rt")) return &ctx->bcback_rt;
+    if (!strcmp(key, "gemm_staged")) return &ctx->gemm_staged;
     if (!strcmp(key, "orgsb_nb")) return &ctx->orgsb_nb;
     if (!strcmp(key, "batch_streams")) return &ctx->batch_streams;
     if (!strcmp(key, "batch_graph")) return &ctx->batch_graph;
@@ -138,11 +139,12 @@ evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value)
     if ((slot == &ctx->bcback_group && value != 0 && value != 32 && value != 64) ||
         (slot == &ctx->bcback_rows && value != 0 && value != 64 && value != 128) ||
         (slot == &ctx->bcback_sub && value != 0 && value != 16 && value != 32 && value != 64) ||
-        (slot == &ctx->bcback_rt && value > 2)) {
+        (slot == &ctx->bcback_rt && value > 2) || (slot == &ctx->gemm_staged && value > 1)) {
         ctx->last_invalid_arg = 3;
         return EVD_ERR_INVALID_ARG;
     }
     *slot = value;
+    if (slot == &ctx->gemm_staged) gemm_set_staged((int)value);
     if (slot == &ctx->last_hip_error && value == 0) evd_tls_hip_error = 0;
     ctx->last_invalid_arg = 0;
     return EVD_OK;
@@ -203,13 +205,14 @@ evd_status_t evd_dgemm(evd_ctx_t ctx, char opa, char opb, int lower_c, int64_t m
     else if (m > 0 && n > 0 && !C) bad = 14;
     else if (ldc < (m > 1 ? m : 1)) bad = 15;
     else if (lower_c && m != n) bad = 4;
+    else if (lower_c == 2 && (oa != OP_N || ob != OP_T)) bad = 4;
     if (bad) { ctx->last_invalid_arg = bad; return EVD_ERR_INVALID_ARG; }
     if (oa == OP_S && ob == OP_T) { /* supported */ }
     if (oa == OP_S && lower_c) { ctx->last_invalid_arg = 4; return EVD_ERR_INVALID_ARG; }
     if (ctx->device < 0) return EVD_ERR_HIP;
     EVD_CHECK(evd_hip(ctx, hipSetDevice(ctx->device)));
-    return gemm_f64(ctx->stream, oa, ob, lower_c ? 1 : 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double *)work,
-                    work ? work_bytes / sizeof(double) : 0);
+    return gemm_f64(ctx->stream, oa, ob, lower_c == 2 ? 2 : (lower_c ? 1 : 0), m, n, k, alpha, A, lda, B, ldb, beta, C,
+                    ldc, (double *)work, work ? work_bytes / sizeof(double) : 0);
 }
 
 }  // extern "C"

@@ -190,6 +190,7 @@ struct evd_ctx_s {
     int64_t bcback_valu;      // 1 = reflector-by-reflector BC-back on the vector ALUs (0 = blocked MFMA)
     int64_t bcback_sub;       // sweeps per block reflector inside a 64-sweep group (0 = 32, 16, 32, 64)
     int64_t bcback_rt;        // 16-row tiles per wavefront of the 64-sweep BC-back (0 = 1, 1, 2)
+    int64_t gemm_staged;      // 1: FP64 GEMM main loop staged through registers everywhere (process-wide; 0 = direct-to-LDS loads for whole tiles)
     int64_t batch_streams;    // streams used by the batched driver (0 = 4)
     int64_t batch_graph;      // 1 = capture the batched launch sequence in a hipGraph
     int64_t last_graph_used;  // 1 if the last batched call ran from a graph
@@ -323,6 +324,7 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
 size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k);
 // compute units the split-K planner fills (called when a context is created)
 void gemm_set_cu_count(int cus);
+void gemm_set_staged(int on);
 // Row (within a 16 x 16 tile) held by lane group lq = lane/16, element r, of
 // the FP32 accumulator of v_mfma_f32_16x16x32_bf16.
 #define EVD_F32_MFMA_ROW(lq, r) (4 * (lq) + (r))

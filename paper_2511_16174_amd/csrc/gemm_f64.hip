@@ -29,6 +29,7 @@ constexpr int BK = 16;
 constexpr int PAD = 1;
 int g_gemm_swizzle = 1;  // XCD-aware tile order (gemm_tile); not used for triangular outputs, where it was slower
 int g_gemm_cus = 256;    // compute units of the device (set when a context is created)
+int g_gemm_dl = 1;       // direct-to-LDS kernel for 128 x 128 tiles (0: main loop staged through registers)
 
 // waves per SIMD to budget registers for: 8-wavefront tiles (two workgroups
 // per CU, four waves per SIMD) fit 128 VGPRs, 4-wavefront tiles 256; the
@@ -36,6 +37,41 @@ int g_gemm_cus = 256;    // compute units of the device (set when a context is c
 constexpr int gemm_min_waves(int BM, int BN, int WM, int WN, int OPA)
 {
     return ((BM / WM) * (BN / WN) >= 8 ? 4 : 2) / (OPA == OP_S ? 2 : 1);
+}
+
+// Epilogue of a wavefront's WM x WN sub-tile at (mw, nw): lane holds
+// C(mw + i 16 + lane % 16, nw + j 16 + lane / 16 + 4 r), r = 0..3.  Entries
+// are stored inside C, at rows >= mlo and columns >= nlo (a tile moved back
+// to fit inside C stores only what the tile before it does not), and on or
+// below the diagonal for LOWER (LOWER = 2 also stores the transpose).
+template <int WM, int WN, int TM, int TN, int LOWER>
+__device__ __forceinline__ void gemm_epilogue(const double4_t (&acc)[TM][TN], int64_t m, int64_t n, int64_t mw,
+                                              int64_t nw, int64_t mlo, int64_t nlo, double alpha, double beta,
+                                              double *__restrict__ C, int64_t ldc, int lane)
+{
+    const int lr = lane & 15, lq = lane >> 4;
+    double *Cw = C + mw + nw * ldc;
+    const int ildc = (int)ldc;
+    const bool cfull = (mw + WM <= m) && (nw + WN <= n) && mw >= mlo && nw >= nlo && (!LOWER || mw >= nw + WN - 1);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int li = i * 16 + lr;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int lj = j * 16 + lq + 4 * r;
+                const int64_t gi = mw + li, gj = nw + lj;
+                if (cfull || (gi < m && gj < n && gi >= mlo && gj >= nlo && (!LOWER || gi >= gj))) {
+                    double *cp = Cw + (li + lj * ildc);
+                    double v = alpha * acc[i][j][r];
+                    if (beta != 0.0) v += beta * (*cp);
+                    *cp = v;
+                    if (LOWER == 2 && gi > gj) C[gj + gi * ldc] = v;  // mirror into the upper triangle
+                }
+            }
+        }
+    }
 }
 
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
@@ -160,31 +196,7 @@ __device__ __forceinline__ void gemm_body(int64_t m, int64_t n, int64_t k, int64
         }
     }
 
-    // epilogue: lane holds C(i0 + lane%16, j0 + lane/16 + 4 r), r = 0..3
-    const int lr = lane & 15, lq = lane >> 4;
-    const int64_t mw = m0 + wm * WM, nw = n0 + wn * WN;
-    double *Cw = C + mw + nw * ldc;
-    const int ildc = (int)ldc;
-    const bool cfull = (mw + WM <= m) && (nw + WN <= n) && (!LOWER || mw >= nw + WN - 1);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int li = i * 16 + lr;
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int lj = j * 16 + lq + 4 * r;
-                const int64_t gi = mw + li, gj = nw + lj;
-                if (cfull || (gi < m && gj < n && (!LOWER || gi >= gj))) {
-                    double *cp = Cw + (li + lj * ildc);
-                    double v = alpha * acc[i][j][r];
-                    if (beta != 0.0) v += beta * (*cp);
-                    *cp = v;
-                    if (LOWER == 2 && gi > gj) C[gj + gi * ldc] = v;  // mirror into the upper triangle
-                }
-            }
-        }
-    }
+    gemm_epilogue<WM, WN, TM, TN, LOWER>(acc, m, n, m0 + wm * WM, n0 + wn * WN, m0, n0, alpha, beta, C, ldc, lane);
 }
 
 // Output tile of this workgroup.  Workgroups are dispatched round-robin over
@@ -242,6 +254,138 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, 
     const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
     gemm_body<BM, BN, WM, WN, OPA, OPB, LOWER>(m, n, k, kbeg, kend, m0, n0, alpha, A, lda, B, ldb, beta,
                                                C + (int64_t)blockIdx.z * split_stride, ldc);
+}
+
+// ------------------------------------------------ direct-to-LDS main loop
+// 128 x 128 tiles whose K slices of 16 are all whole are multiplied from
+// slices that buffer loads write straight into LDS (buffer_load_dwordx4 ...
+// lds): no staging registers and no LDS stores, and the loads of slice t + 1
+// are in flight while slice t is multiplied.  One load instruction of a
+// wavefront moves 1 KB: lane l's 16 bytes land 16 l bytes after the
+// instruction's LDS address, whatever global address the lane reads.  Two
+// layouts:
+//  * MN, operand contiguous along the tile's M (or N): stage[k][d], one
+//    column of 128 per instruction, rows padded to 144 doubles so that the
+//    two half-wavefronts of a fragment read (k and k + 1) use different LDS
+//    banks;
+//  * K, operand contiguous along K: stage[d][16], 8 rows of 16 per
+//    instruction; the k-pair p of row d sits in slot p ^ ((d >> 1) & 7) (the
+//    lane picks its global address to match), so that the 16 rows a fragment
+//    read touches hit 16 different bank pairs.
+typedef __attribute__((address_space(3))) void lds_void_t;
+constexpr int DL_RS = 144;            // padded MN row (doubles)
+constexpr int DL_STAGE = 16 * DL_RS;  // doubles per operand and stage (>= 128 x 16)
+
+// s_waitcnt on the vector-memory count only (gfx9 encoding)
+__device__ __forceinline__ void wait_vmcnt0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// workgroup barrier without a memory fence: a fence would also wait for the
+// LDS loads still in flight; the empty asm statements keep the compiler from
+// moving LDS accesses across it
+__device__ __forceinline__ void barrier_nofence()
+{
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ __volatile__("" ::: "memory");
+}
+
+// slice of 16 along K of one operand of the tile, origin org, into an LDS
+// stage (8 wavefronts, two instructions each)
+template <bool KLAY>
+__device__ __forceinline__ void dl_issue(const double *org, int64_t ld, double *stage, int wave, int lane)
+{
+    const uint32_t nrec = KLAY ? (uint32_t)((127 * ld + 16) * 8) : (uint32_t)((15 * ld + 128) * 8);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)org, (short)0, (int)nrec,
+                                                                       (int)EVD_BUF_DWORD3);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = 2 * wave + q;  // instruction 0..15 of the slice
+        uint32_t off;
+        double *dst;
+        if (!KLAY) {
+            off = (uint32_t)(2 * lane + c * ld) * 8u;
+            dst = stage + c * DL_RS;
+        } else {
+            const int row = lane >> 3, slot = lane & 7, d = 8 * c + row;
+            off = (uint32_t)(2 * (slot ^ ((d >> 1) & 7)) + d * ld) * 8u;
+            dst = stage + c * 128;
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)dst, 16, (int)off, 0, 0, 0);
+    }
+}
+
+template <bool KLAY>
+__device__ __forceinline__ double dl_frag(const double *stage, int d, int k)
+{
+    if (!KLAY) return stage[k * DL_RS + d];
+    return stage[d * 16 + 2 * ((k >> 1) ^ ((d >> 1) & 7)) + (k & 1)];
+}
+
+// C tile (m0, n0) of 128 x 128, inside C; K range kbeg .. kend of whole
+// slices; 8 wavefronts of 64 x 32 (the same products in the same order as
+// gemm_body, so both main loops give identical results)
+template <int OPA, int OPB, int LOWER>
+__global__ __launch_bounds__(512, gemm_min_waves(128, 128, 64, 32, OPA)) void gemm_f64_dl_kernel(
+    int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
+    int64_t split_stride, int swz)
+{
+    constexpr int WM = 64, WN = 32;
+    constexpr bool AK = (OPA == OP_T), BKL = (OPB == OP_N);
+    __shared__ double smem[4 * DL_STAGE];
+    int bx, by;
+    if (LOWER && swz == 2) gemm_tile_lower(bx, by);
+    else gemm_tile(swz, bx, by);
+    const int64_t mlo = (int64_t)bx * 128, nlo = (int64_t)by * 128;
+    if (LOWER && nlo > mlo + 127) return;  // tile strictly above the diagonal
+    // a tile crossing the edge of C is moved back inside it (m, n >= 128); it
+    // stores only its own rows and columns
+    const int64_t m0 = (mlo + 128 <= m) ? mlo : m - 128, n0 = (nlo + 128 <= n) ? nlo : n - 128;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % 2, wn = wave / 2;
+    const int lr = lane & 15, lk = lane >> 4;
+    auto a_org = [&](int64_t kt) { return AK ? A + kt + m0 * lda : A + m0 + kt * lda; };
+    auto b_org = [&](int64_t kt) { return BKL ? B + kt + n0 * ldb : B + n0 + kt * ldb; };
+    auto stage = [&](int st, int op) { return smem + (2 * st + op) * DL_STAGE; };
+    double4_t acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    const int64_t nkt = (kend > kbeg) ? (kend - kbeg) / BK : 0;
+    if (nkt > 0) {
+        dl_issue<AK>(a_org(kbeg), lda, stage(0, 0), wave, lane);
+        dl_issue<BKL>(b_org(kbeg), ldb, stage(0, 1), wave, lane);
+    }
+    for (int64_t t = 0; t < nkt; ++t) {
+        const int st = (int)(t & 1);
+        // this wavefront's loads of slice t have landed; past the barrier all
+        // of them have, and no wavefront still reads the other stage
+        wait_vmcnt0();
+        barrier_nofence();
+        if (t + 1 < nkt) {
+            dl_issue<AK>(a_org(kbeg + (t + 1) * BK), lda, stage(st ^ 1, 0), wave, lane);
+            dl_issue<BKL>(b_org(kbeg + (t + 1) * BK), ldb, stage(st ^ 1, 1), wave, lane);
+        }
+        const double *As = stage(st, 0), *Bs = stage(st, 1);
+#pragma unroll
+        for (int k4 = 0; k4 < BK; k4 += 4) {
+            double fa[4], fb[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fa[i] = dl_frag<AK>(As, wm * WM + i * 16 + lr, k4 + lk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) fb[j] = dl_frag<BKL>(Bs, wn * WN + j * 16 + lr, k4 + lk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i], acc[i][j], 0, 0, 0);
+        }
+    }
+    gemm_epilogue<WM, WN, 4, 2, LOWER>(acc, m, n, m0 + wm * WM, n0 + wn * WN, mlo, nlo, alpha, beta,
+                                       C + (int64_t)blockIdx.z * split_stride, ldc, lane);
 }
 
 // Grouped product with sizes in device memory: problem blockIdx.z, C = A B
@@ -317,6 +461,22 @@ void launch_cfg(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64
     }
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, OPA, OPB, LOWER>), grid, dim3(NT), 0, s, m, n, k, kchunk,
                        alpha, A, lda, B, ldb, beta, C, ldc, split_stride, swz);
+}
+
+// direct-load kernel for 128 x 128 tiles (op N or T, m, n >= 128, whole K slices)
+template <int OPA, int OPB, int LOWER>
+void launch_dl(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha,
+               const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+               int64_t split_stride)
+{
+    int swz = LOWER ? 0 : g_gemm_swizzle;
+    if (LOWER && grid.z == 1 && m == n) {
+        const unsigned T = grid.x;
+        grid = dim3(T * (T + 1) / 2, 1, 1);
+        swz = 2;
+    }
+    hipLaunchKernelGGL((gemm_f64_dl_kernel<OPA, OPB, LOWER>), grid, dim3(512), 0, s, m, n, k, kchunk, alpha, A, lda, B,
+                       ldb, beta, C, ldc, split_stride, swz);
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -410,6 +570,8 @@ void gemm_set_cu_count(int cus)
     if (cus > 0) g_gemm_cus = cus;
 }
 
+void gemm_set_staged(int on) { g_gemm_dl = on ? 0 : 1; }
+
 size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k)
 {
     GemmPlan p = plan_gemm(m, n, k, (size_t)-1);
@@ -448,7 +610,23 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         a = 1.0;
         bta = 0.0;
     }
-    if (p.bm == 128 && p.bn == 128)
+    const bool dl = g_gemm_dl && p.bm == 128 && p.bn == 128 && m >= 128 && n >= 128 && opa != OP_S && k % BK == 0 &&
+                    p.kchunk % BK == 0;
+    if (dl) {
+#define EVD_DL_CASE(OA, OB, LW)                                                                                \
+    if (opa == OA && opb == OB && lower == LW)                                                                 \
+        launch_dl<OA, OB, LW>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
+        EVD_DL_CASE(OP_N, OP_N, 0)
+        EVD_DL_CASE(OP_N, OP_T, 0)
+        EVD_DL_CASE(OP_T, OP_N, 0)
+        EVD_DL_CASE(OP_T, OP_T, 0)
+        EVD_DL_CASE(OP_N, OP_N, 1)
+        EVD_DL_CASE(OP_N, OP_T, 1)
+        EVD_DL_CASE(OP_T, OP_N, 1)
+        EVD_DL_CASE(OP_T, OP_T, 1)
+        EVD_DL_CASE(OP_N, OP_T, 2)
+#undef EVD_DL_CASE
+    } else if (p.bm == 128 && p.bn == 128)
         launch_ops<128, 128, 64, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
                                      sstride);
     else if (p.bm == 128 && p.bn == 64)

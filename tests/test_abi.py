@@ -61,7 +61,8 @@ def test_params(vctx):
     assert lib.evd_set_param(h, b"b", -1) == evd.EVD_ERR_INVALID_ARG
     assert lib.evd_last_invalid_arg(h) == 3
     for key, good, bad in ((b"bcback_group", (0, 32, 64), (16, 48)), (b"bcback_rows", (0, 64, 128), (32, 96)),
-                           (b"bcback_sub", (0, 16, 32, 64), (8, 48)), (b"bcback_rt", (0, 1, 2), (3, 4))):
+                           (b"bcback_sub", (0, 16, 32, 64), (8, 48)), (b"bcback_rt", (0, 1, 2), (3, 4)),
+                           (b"gemm_staged", (0, 1), (2, 5))):
         for v in good:
             assert lib.evd_set_param(h, key, v) == evd.EVD_OK
         for v in bad:
@@ -102,6 +103,8 @@ def test_bcback_work_size_and_argument_checks(vctx):
     ((b"N", b"N", 0, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 2), 15),
     ((b"S", b"N", 0, 4, 4, 5, 1.0, 8, 4, 8, 5, 0.0, 8, 4), 7),
     ((b"N", b"N", 1, 4, 5, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4), 4),
+    ((b"N", b"N", 2, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4), 4),   # mirrored lower mode needs op(B) = B^T
+    ((b"T", b"T", 2, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4), 4),
 ])
 def test_dgemm_argument_checks(vctx, args, bad):
     lib, h = vctx

@@ -110,3 +110,50 @@ def test_dgemm_many_splits_small_outputs(m, n, k, opa, lower, alpha, beta):
         assert np.array_equal(out[~mask], C0[~mask])
     else:
         assert np.max(np.abs(out - ref)) <= tol
+
+
+@pytest.mark.parametrize("opa,opb,lower,m,n,k,beta", [
+    ("N", "N", 0, 2900, 3001, 640, 0.5), ("T", "N", 0, 3000, 2950, 512, 0.0), ("N", "T", 2, 3001, 3001, 640, 1.0),
+    ("N", "T", 1, 2900, 2900, 256, -1.0), ("T", "T", 0, 2950, 2900, 48, 1.0), ("N", "N", 0, 3200, 3200, 4096, 1.0),
+    ("N", "N", 0, 2900, 2900, 650, 1.0)])
+def test_dgemm_direct_lds_matches_staged(opa, opb, lower, m, n, k, beta):
+    """128 x 128 tiles with whole K slices of 16 run the kernel whose slices
+    are loaded straight into LDS (tiles crossing the edge of C moved back
+    inside it); it performs the same products in the same order as the main
+    loop staged through registers ("gemm_staged" = 1), so both give the same
+    bits; a K split (3200^2 x 4096 with workspace), the lower-triangle modes
+    and a K that is not a multiple of 16 (staged path either way) included."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    rng = np.random.default_rng(m + 3 * n + k)
+    A = rng.standard_normal((m, k) if opa == "N" else (k, m))
+    B = rng.standard_normal((k, n) if opb == "N" else (n, k))
+    C0 = rng.standard_normal((m, n))
+    alpha = -0.75
+    dA, dB = dev(A), dev(B)
+    wb = ctx.evd_dgemm_work_size(m, n, k)
+    work = torch.empty(max(wb // 8, 1), dtype=torch.float64, device="cuda")
+    outs = []
+    try:
+        for staged in (0, 1):
+            ctx.set_param("gemm_staged", staged)
+            dC = dev(C0)
+            ctx.evd_dgemm(opa, opb, lower, m, n, k, alpha, dA, A.shape[0], dB, B.shape[0], beta, dC, m, work, wb)
+            torch.cuda.synchronize()
+            outs.append(host(dC, m, n))
+    finally:
+        ctx.set_param("gemm_staged", 0)
+    assert np.array_equal(outs[0], outs[1])
+    opA = A if opa == "N" else A.T
+    opB = B if opb == "N" else B.T
+    ref = alpha * (opA @ opB) + beta * C0
+    tol = 4 * k * np.finfo(float).eps * np.abs(opA).max() * np.abs(opB).max() * 4 + 1e-12
+    if lower:
+        mask = np.tril(np.ones((m, n), bool))
+        assert np.max(np.abs(outs[0][mask] - ref[mask])) <= tol
+        if lower == 2:
+            assert np.array_equal(outs[0][~mask], outs[0].T[~mask])
+        else:
+            assert np.array_equal(outs[0][~mask], C0[~mask])
+    else:
+        assert np.max(np.abs(outs[0] - ref)) <= tol
