@@ -291,15 +291,18 @@ __device__ __forceinline__ void barrier_nofence()
 
 // slice of 16 along K of one operand of the tile, origin org, into an LDS
 // stage (8 wavefronts, two instructions each)
-template <bool KLAY>
+// (D: the tile's extent along M or N; 128, or 64 with the K layout)
+template <bool KLAY, int D>
 __device__ __forceinline__ void dl_issue(const double *org, int64_t ld, double *stage, int wave, int lane)
 {
-    const uint32_t nrec = KLAY ? (uint32_t)((127 * ld + 16) * 8) : (uint32_t)((15 * ld + 128) * 8);
+    static_assert(D == 128 || (KLAY && D == 64), "direct-load tile extent");
+    constexpr int PER = D * 16 / 128 / 8;  // 1 KB instructions per wavefront
+    const uint32_t nrec = KLAY ? (uint32_t)(((D - 1) * ld + 16) * 8) : (uint32_t)((15 * ld + 128) * 8);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)org, (short)0, (int)nrec,
                                                                        (int)EVD_BUF_DWORD3);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int c = 2 * wave + q;  // instruction 0..15 of the slice
+    for (int q = 0; q < PER; ++q) {
+        const int c = PER * wave + q;  // instruction of the slice
         uint32_t off;
         double *dst;
         if (!KLAY) {
@@ -324,40 +327,42 @@ __device__ __forceinline__ double dl_frag(const double *stage, int d, int k)
 // C tile (m0, n0) of 128 x 128, inside C; K range kbeg .. kend of whole
 // slices; 8 wavefronts of 64 x 32 (the same products in the same order as
 // gemm_body, so both main loops give identical results)
-template <int OPA, int OPB, int LOWER>
-__global__ __launch_bounds__(512, gemm_min_waves(128, 128, 64, 32, OPA)) void gemm_f64_dl_kernel(
+template <int OPA, int OPB, int LOWER, int BN>
+__global__ __launch_bounds__(512, gemm_min_waves(128, BN, BN == 128 ? 64 : 32, 32, OPA)) void gemm_f64_dl_kernel(
     int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
     int64_t split_stride, int swz)
 {
-    constexpr int WM = 64, WN = 32;
+    constexpr int WM = BN == 128 ? 64 : 32, WN = 32, TM = WM / 16, TN = WN / 16, NWM = 128 / WM;
     constexpr bool AK = (OPA == OP_T), BKL = (OPB == OP_N);
-    __shared__ double smem[4 * DL_STAGE];
+    static_assert(BN == 128 || (BN == 64 && BKL && !LOWER), "64-wide tiles: op(B) = B, full C");
+    constexpr int SA = DL_STAGE, SB = BN == 128 ? DL_STAGE : BN * 16, SS = SA + SB;
+    __shared__ double smem[2 * SS];
     int bx, by;
     if (LOWER && swz == 2) gemm_tile_lower(bx, by);
     else gemm_tile(swz, bx, by);
-    const int64_t mlo = (int64_t)bx * 128, nlo = (int64_t)by * 128;
+    const int64_t mlo = (int64_t)bx * 128, nlo = (int64_t)by * BN;
     if (LOWER && nlo > mlo + 127) return;  // tile strictly above the diagonal
-    // a tile crossing the edge of C is moved back inside it (m, n >= 128); it
-    // stores only its own rows and columns
-    const int64_t m0 = (mlo + 128 <= m) ? mlo : m - 128, n0 = (nlo + 128 <= n) ? nlo : n - 128;
+    // a tile crossing the edge of C is moved back inside it (m >= 128,
+    // n >= BN); it stores only its own rows and columns
+    const int64_t m0 = (mlo + 128 <= m) ? mlo : m - 128, n0 = (nlo + BN <= n) ? nlo : n - BN;
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
     const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % 2, wn = wave / 2;
+    const int wm = wave % NWM, wn = wave / NWM;
     const int lr = lane & 15, lk = lane >> 4;
     auto a_org = [&](int64_t kt) { return AK ? A + kt + m0 * lda : A + m0 + kt * lda; };
     auto b_org = [&](int64_t kt) { return BKL ? B + kt + n0 * ldb : B + n0 + kt * ldb; };
-    auto stage = [&](int st, int op) { return smem + (2 * st + op) * DL_STAGE; };
-    double4_t acc[4][2];
+    auto stage = [&](int st, int op) { return smem + st * SS + op * SA; };
+    double4_t acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
     const int64_t nkt = (kend > kbeg) ? (kend - kbeg) / BK : 0;
     if (nkt > 0) {
-        dl_issue<AK>(a_org(kbeg), lda, stage(0, 0), wave, lane);
-        dl_issue<BKL>(b_org(kbeg), ldb, stage(0, 1), wave, lane);
+        dl_issue<AK, 128>(a_org(kbeg), lda, stage(0, 0), wave, lane);
+        dl_issue<BKL, BN>(b_org(kbeg), ldb, stage(0, 1), wave, lane);
     }
     for (int64_t t = 0; t < nkt; ++t) {
         const int st = (int)(t & 1);
@@ -366,25 +371,25 @@ __global__ __launch_bounds__(512, gemm_min_waves(128, 128, 64, 32, OPA)) void ge
         wait_vmcnt0();
         barrier_nofence();
         if (t + 1 < nkt) {
-            dl_issue<AK>(a_org(kbeg + (t + 1) * BK), lda, stage(st ^ 1, 0), wave, lane);
-            dl_issue<BKL>(b_org(kbeg + (t + 1) * BK), ldb, stage(st ^ 1, 1), wave, lane);
+            dl_issue<AK, 128>(a_org(kbeg + (t + 1) * BK), lda, stage(st ^ 1, 0), wave, lane);
+            dl_issue<BKL, BN>(b_org(kbeg + (t + 1) * BK), ldb, stage(st ^ 1, 1), wave, lane);
         }
         const double *As = stage(st, 0), *Bs = stage(st, 1);
 #pragma unroll
         for (int k4 = 0; k4 < BK; k4 += 4) {
-            double fa[4], fb[2];
+            double fa[TM], fb[TN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = dl_frag<AK>(As, wm * WM + i * 16 + lr, k4 + lk);
+            for (int i = 0; i < TM; ++i) fa[i] = dl_frag<AK>(As, wm * WM + i * 16 + lr, k4 + lk);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) fb[j] = dl_frag<BKL>(Bs, wn * WN + j * 16 + lr, k4 + lk);
+            for (int j = 0; j < TN; ++j) fb[j] = dl_frag<BKL>(Bs, wn * WN + j * 16 + lr, k4 + lk);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i], acc[i][j], 0, 0, 0);
         }
     }
-    gemm_epilogue<WM, WN, 4, 2, LOWER>(acc, m, n, m0 + wm * WM, n0 + wn * WN, mlo, nlo, alpha, beta,
+    gemm_epilogue<WM, WN, TM, TN, LOWER>(acc, m, n, m0 + wm * WM, n0 + wn * WN, mlo, nlo, alpha, beta,
                                        C + (int64_t)blockIdx.z * split_stride, ldc, lane);
 }
 
@@ -463,8 +468,8 @@ void launch_cfg(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64
                        alpha, A, lda, B, ldb, beta, C, ldc, split_stride, swz);
 }
 
-// direct-load kernel for 128 x 128 tiles (op N or T, m, n >= 128, whole K slices)
-template <int OPA, int OPB, int LOWER>
+// direct-load kernel for 128 x BN tiles (op N or T, m >= 128, n >= BN, whole K slices)
+template <int OPA, int OPB, int LOWER, int BN>
 void launch_dl(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha,
                const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
                int64_t split_stride)
@@ -475,7 +480,7 @@ void launch_dl(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64_
         grid = dim3(T * (T + 1) / 2, 1, 1);
         swz = 2;
     }
-    hipLaunchKernelGGL((gemm_f64_dl_kernel<OPA, OPB, LOWER>), grid, dim3(512), 0, s, m, n, k, kchunk, alpha, A, lda, B,
+    hipLaunchKernelGGL((gemm_f64_dl_kernel<OPA, OPB, LOWER, BN>), grid, dim3(512), 0, s, m, n, k, kchunk, alpha, A, lda, B,
                        ldb, beta, C, ldc, split_stride, swz);
 }
 
@@ -615,7 +620,7 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
     if (dl) {
 #define EVD_DL_CASE(OA, OB, LW)                                                                                \
     if (opa == OA && opb == OB && lower == LW)                                                                 \
-        launch_dl<OA, OB, LW>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
+        launch_dl<OA, OB, LW, 128>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
         EVD_DL_CASE(OP_N, OP_N, 0)
         EVD_DL_CASE(OP_N, OP_T, 0)
         EVD_DL_CASE(OP_T, OP_N, 0)
@@ -626,6 +631,10 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         EVD_DL_CASE(OP_T, OP_T, 1)
         EVD_DL_CASE(OP_N, OP_T, 2)
 #undef EVD_DL_CASE
+    } else if (g_gemm_dl && p.bm == 128 && p.bn == 64 && m >= 128 && n >= 64 && opb == OP_N && lower == 0 &&
+               opa != OP_S && k % BK == 0 && p.kchunk % BK == 0) {
+        if (opa == OP_N) launch_dl<OP_N, OP_N, 0, 64>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
+        else launch_dl<OP_T, OP_N, 0, 64>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
     } else if (p.bm == 128 && p.bn == 128)
         launch_ops<128, 128, 64, 32>(s, opa, opb, lower, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo,
                                      sstride);
