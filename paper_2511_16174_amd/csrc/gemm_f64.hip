@@ -327,53 +327,87 @@ __device__ __forceinline__ double dl_frag(const double *stage, int d, int k)
 // C tile (m0, n0) of 128 x 128, inside C; K range kbeg .. kend of whole
 // slices; 8 wavefronts of 64 x 32 (the same products in the same order as
 // gemm_body, so both main loops give identical results)
+// Last, partial K slice (krem < 16 columns of K): slots past krem are
+// zero-filled.  MN layout: a whole instruction per K column, so invalid
+// columns take an offset beyond the descriptor.  K layout: the two columns of
+// a k-pair share 16 bytes, so the slice moves as 4-byte words, each with its
+// own validity (four instructions per 1 KB).
+template <bool KLAY, int D>
+__device__ __forceinline__ void dl_issue_tail(const double *org, int64_t ld, double *stage, int wave, int lane,
+                                              int krem)
+{
+    constexpr int PER = D * 16 / 128 / 8;
+    const uint32_t nrec = KLAY ? (uint32_t)(((D - 1) * ld + 16) * 8) : (uint32_t)((15 * ld + 128) * 8);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)org, (short)0, (int)nrec,
+                                                                       (int)EVD_BUF_DWORD3);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = PER * wave + q;
+        if (!KLAY) {
+            const uint32_t off = (c < krem) ? (uint32_t)(2 * lane + c * ld) * 8u : EVD_BUF_OOB;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)(stage + c * DL_RS), 16, (int)off, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int w = 64 * j + lane;  // word of the 1 KB chunk
+                const int row = w >> 5, slot = (w >> 2) & 7, h = w & 3, d = 8 * c + row;
+                const int kk = 2 * (slot ^ ((d >> 1) & 7)) + (h >> 1);
+                const uint32_t off =
+                    (kk < krem) ? (uint32_t)(kk + d * ld) * 8u + 4u * (uint32_t)(h & 1) : EVD_BUF_OOB;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)(stage + c * 128 + 32 * j), 4, (int)off,
+                                                         0, 0, 0);
+            }
+        }
+    }
+}
+
+// One 128 x BN tile of C from K columns kbeg .. kend (a partial last slice is
+// zero-filled): tile (mlo, nlo), moved back inside C when it crosses the edge
+// (m >= 128, n >= BN), storing only its own entries; smem holds 2 stages.
+// The products are those of gemm_body, in the same order, so both main loops
+// give the same bits.
 template <int OPA, int OPB, int LOWER, int BN>
-__global__ __launch_bounds__(512, gemm_min_waves(128, BN, BN == 128 ? 64 : 32, 32, OPA)) void gemm_f64_dl_kernel(
-    int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
-    const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
-    int64_t split_stride, int swz)
+__device__ __forceinline__ void gemm_dl_tile(int64_t m, int64_t n, int64_t kbeg, int64_t kend, int64_t mlo,
+                                             int64_t nlo, double alpha, const double *__restrict__ A, int64_t lda,
+                                             const double *__restrict__ B, int64_t ldb, double beta,
+                                             double *__restrict__ C, int64_t ldc, double *smem)
 {
     constexpr int WM = BN == 128 ? 64 : 32, WN = 32, TM = WM / 16, TN = WN / 16, NWM = 128 / WM;
     constexpr bool AK = (OPA == OP_T), BKL = (OPB == OP_N);
     static_assert(BN == 128 || (BN == 64 && BKL && !LOWER), "64-wide tiles: op(B) = B, full C");
     constexpr int SA = DL_STAGE, SB = BN == 128 ? DL_STAGE : BN * 16, SS = SA + SB;
-    __shared__ double smem[2 * SS];
-    int bx, by;
-    if (LOWER && swz == 2) gemm_tile_lower(bx, by);
-    else gemm_tile(swz, bx, by);
-    const int64_t mlo = (int64_t)bx * 128, nlo = (int64_t)by * BN;
-    if (LOWER && nlo > mlo + 127) return;  // tile strictly above the diagonal
-    // a tile crossing the edge of C is moved back inside it (m >= 128,
-    // n >= BN); it stores only its own rows and columns
     const int64_t m0 = (mlo + 128 <= m) ? mlo : m - 128, n0 = (nlo + BN <= n) ? nlo : n - BN;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-    const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % NWM, wn = wave / NWM;
     const int lr = lane & 15, lk = lane >> 4;
     auto a_org = [&](int64_t kt) { return AK ? A + kt + m0 * lda : A + m0 + kt * lda; };
     auto b_org = [&](int64_t kt) { return BKL ? B + kt + n0 * ldb : B + n0 + kt * ldb; };
     auto stage = [&](int st, int op) { return smem + st * SS + op * SA; };
+    const int64_t klen = (kend > kbeg) ? kend - kbeg : 0;
+    const int64_t nkt = (klen + BK - 1) / BK;
+    const int krem = (int)(klen - (nkt - 1) * BK);  // columns of the last slice
+    auto issue = [&](int64_t t, int st) {
+        if (t + 1 < nkt || krem == BK) {
+            dl_issue<AK, 128>(a_org(kbeg + t * BK), lda, stage(st, 0), wave, lane);
+            dl_issue<BKL, BN>(b_org(kbeg + t * BK), ldb, stage(st, 1), wave, lane);
+        } else {
+            dl_issue_tail<AK, 128>(a_org(kbeg + t * BK), lda, stage(st, 0), wave, lane, krem);
+            dl_issue_tail<BKL, BN>(b_org(kbeg + t * BK), ldb, stage(st, 1), wave, lane, krem);
+        }
+    };
     double4_t acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
-    const int64_t nkt = (kend > kbeg) ? (kend - kbeg) / BK : 0;
-    if (nkt > 0) {
-        dl_issue<AK, 128>(a_org(kbeg), lda, stage(0, 0), wave, lane);
-        dl_issue<BKL, BN>(b_org(kbeg), ldb, stage(0, 1), wave, lane);
-    }
+    if (nkt > 0) issue(0, 0);
     for (int64_t t = 0; t < nkt; ++t) {
         const int st = (int)(t & 1);
         // this wavefront's loads of slice t have landed; past the barrier all
         // of them have, and no wavefront still reads the other stage
         wait_vmcnt0();
         barrier_nofence();
-        if (t + 1 < nkt) {
-            dl_issue<AK, 128>(a_org(kbeg + (t + 1) * BK), lda, stage(st ^ 1, 0), wave, lane);
-            dl_issue<BKL, BN>(b_org(kbeg + (t + 1) * BK), ldb, stage(st ^ 1, 1), wave, lane);
-        }
+        if (t + 1 < nkt) issue(t + 1, st ^ 1);
         const double *As = stage(st, 0), *Bs = stage(st, 1);
 #pragma unroll
         for (int k4 = 0; k4 < BK; k4 += 4) {
@@ -389,16 +423,50 @@ __global__ __launch_bounds__(512, gemm_min_waves(128, BN, BN == 128 ? 64 : 32, 3
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i], acc[i][j], 0, 0, 0);
         }
     }
-    gemm_epilogue<WM, WN, TM, TN, LOWER>(acc, m, n, m0 + wm * WM, n0 + wn * WN, mlo, nlo, alpha, beta,
-                                       C + (int64_t)blockIdx.z * split_stride, ldc, lane);
+    gemm_epilogue<WM, WN, TM, TN, LOWER>(acc, m, n, m0 + wm * WM, n0 + wn * WN, mlo, nlo, alpha, beta, C, ldc, lane);
+}
+
+template <int BN>
+constexpr int dl_lds_elems() { return 2 * (DL_STAGE + (BN == 128 ? DL_STAGE : BN * 16)); }
+
+template <int OPA, int OPB, int LOWER, int BN>
+__global__ __launch_bounds__(512, gemm_min_waves(128, BN, BN == 128 ? 64 : 32, 32, OPA)) void gemm_f64_dl_kernel(
+    int64_t m, int64_t n, int64_t k, int64_t kchunk, double alpha, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
+    int64_t split_stride, int swz)
+{
+    __shared__ double smem[dl_lds_elems<BN>()];
+    int bx, by;
+    if (LOWER && swz == 2) gemm_tile_lower(bx, by);
+    else gemm_tile(swz, bx, by);
+    const int64_t mlo = (int64_t)bx * 128, nlo = (int64_t)by * BN;
+    if (LOWER && nlo > mlo + 127) return;  // tile strictly above the diagonal
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = (kbeg + kchunk < k) ? kbeg + kchunk : k;
+    gemm_dl_tile<OPA, OPB, LOWER, BN>(m, n, kbeg, kend, mlo, nlo, alpha, A, lda, B, ldb, beta,
+                                      C + (int64_t)blockIdx.z * split_stride, ldc, smem);
+}
+
+// Grouped products on the direct-load path: problems with m, n >= 128 (the
+// others are left to gemm_f64_grouped_kernel, which skips these)
+__global__ __launch_bounds__(512, gemm_min_waves(128, 128, 64, 32, OP_N)) void gemm_f64_grouped_dl_kernel(
+    const GemmProblem *probs)
+{
+    __shared__ double smem[dl_lds_elems<128>()];
+    const GemmProblem p = probs[blockIdx.z];
+    if (p.m < 128 || p.n < 128) return;
+    const int64_t mlo = (int64_t)blockIdx.x * 128, nlo = (int64_t)blockIdx.y * 128;
+    if (mlo >= p.m || nlo >= p.n) return;
+    gemm_dl_tile<OP_N, OP_N, 0, 128>(p.m, p.n, 0, p.k, mlo, nlo, 1.0, p.A, p.lda, p.B, p.ldb, 0.0, p.C, p.ldc, smem);
 }
 
 // Grouped product with sizes in device memory: problem blockIdx.z, C = A B
 // (op N, N); tiles outside the problem exit.
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, WM, WN, OP_N)) void gemm_f64_grouped_kernel(const GemmProblem *probs)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, WM, WN, OP_N)) void gemm_f64_grouped_kernel(const GemmProblem *probs, int skip_dl)
 {
     const GemmProblem p = probs[blockIdx.z];
+    if (skip_dl && p.m >= 128 && p.n >= 128) return;  // taken by gemm_f64_grouped_dl_kernel
     const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
     if (m0 >= p.m || n0 >= p.n) return;
     gemm_body<BM, BN, WM, WN, OP_N, OP_N, 0>(p.m, p.n, p.k, 0, p.k, m0, n0, 1.0, p.A, p.lda, p.B, p.ldb, 0.0, p.C,
@@ -561,10 +629,11 @@ evd_status_t gemm_f64_grouped(hipStream_t s, const GemmProblem *probs, int nprob
         const unsigned np = (unsigned)((nprob - p0) < ZMAX ? (nprob - p0) : ZMAX);
         if (max_m > 64 && max_n > 64 && max_m * max_n >= (int64_t)512 * 128 * 128) {
             dim3 grid((unsigned)evd_ceil_div(max_m, 128), (unsigned)evd_ceil_div(max_n, 128), np);
-            hipLaunchKernelGGL((gemm_f64_grouped_kernel<128, 128, 64, 32>), grid, dim3(512), 0, s, probs + p0);
+            if (g_gemm_dl) hipLaunchKernelGGL(gemm_f64_grouped_dl_kernel, grid, dim3(512), 0, s, probs + p0);
+            hipLaunchKernelGGL((gemm_f64_grouped_kernel<128, 128, 64, 32>), grid, dim3(512), 0, s, probs + p0, g_gemm_dl);
         } else {
             dim3 grid((unsigned)evd_ceil_div(max_m, 64), (unsigned)evd_ceil_div(max_n, 64), np);
-            hipLaunchKernelGGL((gemm_f64_grouped_kernel<64, 64, 32, 32>), grid, dim3(256), 0, s, probs + p0);
+            hipLaunchKernelGGL((gemm_f64_grouped_kernel<64, 64, 32, 32>), grid, dim3(256), 0, s, probs + p0, 0);
         }
     }
     return evd_check_last();
@@ -615,7 +684,7 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         a = 1.0;
         bta = 0.0;
     }
-    const bool dl = g_gemm_dl && p.bm == 128 && p.bn == 128 && m >= 128 && n >= 128 && opa != OP_S && k % BK == 0 &&
+    const bool dl = g_gemm_dl && p.bm == 128 && p.bn == 128 && m >= 128 && n >= 128 && opa != OP_S &&
                     p.kchunk % BK == 0;
     if (dl) {
 #define EVD_DL_CASE(OA, OB, LW)                                                                                \
@@ -632,7 +701,7 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         EVD_DL_CASE(OP_N, OP_T, 2)
 #undef EVD_DL_CASE
     } else if (g_gemm_dl && p.bm == 128 && p.bn == 64 && m >= 128 && n >= 64 && opb == OP_N && lower == 0 &&
-               opa != OP_S && k % BK == 0 && p.kchunk % BK == 0) {
+               opa != OP_S && p.kchunk % BK == 0) {
         if (opa == OP_N) launch_dl<OP_N, OP_N, 0, 64>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
         else launch_dl<OP_T, OP_N, 0, 64>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
     } else if (p.bm == 128 && p.bn == 128)

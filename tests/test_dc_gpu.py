@@ -142,3 +142,28 @@ def test_dc_more_merges_than_one_launch_holds():
         Az[:-1] -= z[1:]
         assert np.linalg.norm(Az - w[j] * z) <= 1e-12 * 4.0 * np.sqrt(n)
         assert abs(np.linalg.norm(z) - 1.0) <= 1e-12 * n
+
+
+def test_dc_merge_products_direct_lds_match_staged():
+    """The top merges at n = 6000 run the grouped products on the kernel whose
+    K slices are loaded straight into LDS (a partial last slice zero-filled);
+    the eigenpairs are bit for bit those of the register-staged products
+    ("gemm_staged" = 1), and match the oracle."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    n = 6000
+    rng = np.random.default_rng(6000)
+    d, e = rng.standard_normal(n), rng.standard_normal(n - 1)
+    out = []
+    try:
+        for staged in (0, 1):
+            ctx.set_param("gemm_staged", staged)
+            out.append(run_dc(d, e))
+    finally:
+        ctx.set_param("gemm_staged", 0)
+    (w0, Z0), (w1, Z1) = out
+    assert np.array_equal(w0, w1) and np.array_equal(Z0, Z1)
+    T = tri(d, e)
+    nrm = np.abs(T).sum(axis=1).max()
+    assert M.residual(T, w0, Z0) <= 10 and M.orthogonality(Z0) <= 10
+    assert np.max(np.abs(np.sort(w0) - np.linalg.eigvalsh(T))) <= 1e-12 * nrm

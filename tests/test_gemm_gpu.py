@@ -116,14 +116,16 @@ def test_dgemm_many_splits_small_outputs(m, n, k, opa, lower, alpha, beta):
     ("N", "N", 0, 2900, 3001, 640, 0.5), ("T", "N", 0, 3000, 2950, 512, 0.0), ("N", "T", 2, 3001, 3001, 640, 1.0),
     ("N", "T", 1, 2900, 2900, 256, -1.0), ("T", "T", 0, 2950, 2900, 48, 1.0), ("N", "N", 0, 3200, 3200, 4096, 1.0),
     ("N", "N", 0, 2900, 2900, 650, 1.0), ("N", "N", 0, 3000, 64, 3008, 0.0), ("T", "N", 0, 2900, 64, 512, 1.0),
-    ("N", "N", 0, 3000, 70, 640, 0.5)])
+    ("N", "N", 0, 3000, 70, 640, 0.5), ("T", "N", 0, 2900, 64, 1003, 1.0), ("N", "T", 1, 2900, 2900, 77, 0.5),
+    ("T", "T", 0, 2950, 2900, 33, 1.0)])
 def test_dgemm_direct_lds_matches_staged(opa, opb, lower, m, n, k, beta):
     """128 x 128 and 128 x 64 tiles with whole K slices of 16 run the kernel
     whose slices are loaded straight into LDS (tiles crossing the edge of C
-    moved back inside it; the m x 64 x m products of SBR included); it performs the same products in the same order as the main
+    moved back inside it; the m x 64 x m products of SBR included; a partial
+    last slice of K zero-filled); it performs the same products in the same order as the main
     loop staged through registers ("gemm_staged" = 1), so both give the same
-    bits; a K split (3200^2 x 4096 with workspace), the lower-triangle modes
-    and a K that is not a multiple of 16 (staged path either way) included."""
+    bits; a K split (3200^2 x 4096 with workspace) and the lower-triangle
+    modes included."""
     from paper_2511_16174_amd import evd
     ctx = evd.context(0)
     rng = np.random.default_rng(m + 3 * n + k)
