@@ -21,6 +21,11 @@
 // op(A) can be A, A^T, or the symmetric matrix held in A's lower triangle
 // (tiles strictly below the diagonal are read directly, tiles strictly above
 // are read transposed from the mirror tile, diagonal tiles element-wise).
+//
+// Large products (128-row tiles, op N or T) take a second kernel of the same
+// tile shapes and MFMA order whose slices are written into LDS by the loads
+// themselves (see the direct-to-LDS main loop below); both give the same
+// bits, and the staged loop above serves the remaining shapes.
 #include "common.h"
 
 namespace {
@@ -257,10 +262,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, 
 }
 
 // ------------------------------------------------ direct-to-LDS main loop
-// 128 x 128 tiles whose K slices of 16 are all whole are multiplied from
-// slices that buffer loads write straight into LDS (buffer_load_dwordx4 ...
-// lds): no staging registers and no LDS stores, and the loads of slice t + 1
-// are in flight while slice t is multiplied.  One load instruction of a
+// 128 x 128 and 128 x 64 tiles (op N or T, m >= 128, n >= the tile width)
+// are multiplied from K slices that buffer loads write straight into LDS
+// (buffer_load_dwordx4 ... lds): no staging registers and no LDS stores, and
+// the loads of slice t + 1 are in flight while slice t is multiplied.  One load instruction of a
 // wavefront moves 1 KB: lane l's 16 bytes land 16 l bytes after the
 // instruction's LDS address, whatever global address the lane reads.  Two
 // layouts:
@@ -290,8 +295,8 @@ __device__ __forceinline__ void barrier_nofence()
 }
 
 // slice of 16 along K of one operand of the tile, origin org, into an LDS
-// stage (8 wavefronts, two instructions each)
-// (D: the tile's extent along M or N; 128, or 64 with the K layout)
+// stage, spread over the 8 wavefronts (D: the tile's extent along M or N;
+// 128, or 64 with the K layout)
 template <bool KLAY, int D>
 __device__ __forceinline__ void dl_issue(const double *org, int64_t ld, double *stage, int wave, int lane)
 {
