@@ -325,6 +325,8 @@ size_t gemm_splitk_ws_elems(int64_t m, int64_t n, int64_t k);
 // compute units the split-K planner fills (called when a context is created)
 void gemm_set_cu_count(int cus);
 void gemm_set_staged(int on);
+// lower triangle of the m x m matrix A copied into its upper triangle (sbr.hip)
+evd_status_t evd_mirror_lower_f64(hipStream_t s, int64_t m, double *A, int64_t lda);
 // Row (within a 16 x 16 tile) held by lane group lq = lane/16, element r, of
 // the FP32 accumulator of v_mfma_f32_16x16x32_bf16.
 #define EVD_F32_MFMA_ROW(lq, r) (4 * (lq) + (r))

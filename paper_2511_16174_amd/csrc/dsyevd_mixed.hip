@@ -207,7 +207,10 @@ evd_status_t evd_dsyevd_mixed(evd_ctx_t ctx, char jobz, char uplo, int64_t n, do
     mark(0);
     EVD_CHECK(nonfinite_begin(s, n, A, lda, uplo, w.nflag));
     hipLaunchKernelGGL(mx_down_lower_kernel, g, t, 0, s, n, (const double *)A, lda, w.A32, up ? 1 : 0);
-    if (up) hipLaunchKernelGGL(mx_mirror_upper_kernel, g, t, 0, s, n, A, lda);  // refinement reads the lower triangle
+    // the refinement multiplies by A in full storage (A is overwritten by the
+    // eigenvectors at the end): the stored triangle is copied into the other
+    if (up) hipLaunchKernelGGL(mx_mirror_upper_kernel, g, t, 0, s, n, A, lda);
+    else EVD_CHECK(evd_mirror_lower_f64(s, n, A, lda));
     EVD_CHECK(sbr_run_f32(ctx, 'L', n, b, w.A32, n, w.AB, w.ldab, w.T, w.sbr, w.nflag + 2, nullptr));
     mark(1);
     EVD_CHECK(bc_run_f32(ctx, 'V', n, b, w.AB, w.ldab, w.d, w.e, w.V, w.TAU, w.prog, w.nflag + 2, nullptr));

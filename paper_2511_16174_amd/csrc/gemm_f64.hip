@@ -689,8 +689,9 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         a = 1.0;
         bta = 0.0;
     }
-    const bool dl = g_gemm_dl && p.bm == 128 && p.bn == 128 && m >= 128 && n >= 128 && opa != OP_S &&
-                    p.kchunk % BK == 0;
+    // (split K: every chunk but the last is whole slices; unsplit: any K)
+    const bool kok = p.splits == 1 || p.kchunk % BK == 0;
+    const bool dl = g_gemm_dl && p.bm == 128 && p.bn == 128 && m >= 128 && n >= 128 && opa != OP_S && kok;
     if (dl) {
 #define EVD_DL_CASE(OA, OB, LW)                                                                                \
     if (opa == OA && opb == OB && lower == LW)                                                                 \
@@ -706,7 +707,7 @@ evd_status_t gemm_f64(hipStream_t s, int opa, int opb, int lower_c, int64_t m, i
         EVD_DL_CASE(OP_N, OP_T, 2)
 #undef EVD_DL_CASE
     } else if (g_gemm_dl && p.bm == 128 && p.bn == 64 && m >= 128 && n >= 64 && opb == OP_N && lower == 0 &&
-               opa != OP_S && p.kchunk % BK == 0) {
+               opa != OP_S && kok) {
         if (opa == OP_N) launch_dl<OP_N, OP_N, 0, 64>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
         else launch_dl<OP_T, OP_N, 0, 64>(s, grid, m, n, k, p.kchunk, a, A, lda, B, ldb, bta, Cout, ldo, sstride);
     } else if (p.bm == 128 && p.bn == 128)

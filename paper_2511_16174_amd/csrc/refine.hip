@@ -626,7 +626,8 @@ evd_status_t big_clusters_end(evd_ctx_t ctx, int64_t n, double *E, RefWork &w, c
 
 size_t refine_work_bytes(int64_t n) { return ref_layout(n, nullptr, nullptr); }
 
-// RefSyEv sweeps on X (n x n, ldx), A lower-stored FP64, on the context's
+// RefSyEv sweeps on X (n x n, ldx), A FP64 symmetric in full storage (both
+// triangles; the residual norms read the lower one), on the context's
 // stream, at most max_sweeps of them.  Before each sweep (and after the
 // last) the current X is checked: R = I - X^T X and A X are formed (they are
 // the sweep's first products anyway), lam = the Rayleigh quotients of X's
@@ -655,7 +656,7 @@ evd_status_t refine_run(evd_ctx_t ctx, int64_t n, const double *A, int64_t lda, 
         hipLaunchKernelGGL(oa_eye_kernel, g, t, 0, s, n, R, n);
         EVD_CHECK(gemm_f64(s, OP_T, OP_N, 1, n, n, n, -1.0, X, ldx, X, ldx, 1.0, R, n, nullptr, 0));
         hipLaunchKernelGGL(oa_mirror_kernel, g, t, 0, s, n, R);
-        EVD_CHECK(gemm_f64(s, OP_S, OP_N, 0, n, n, n, 1.0, A, lda, X, ldx, 0.0, AX, n, nullptr, 0));
+        EVD_CHECK(gemm_f64(s, OP_N, OP_N, 0, n, n, n, 1.0, A, lda, X, ldx, 0.0, AX, n, nullptr, 0));
         // check of the current X
         hipLaunchKernelGGL(oa_rayleigh_kernel, dim3((unsigned)n), dim3(64), 0, s, n, (const double *)AX,
                            (const double *)X, ldx, lam);

@@ -741,3 +741,13 @@ evd_status_t evd_dsy2sb(evd_ctx_t ctx, char uplo, int64_t n, int64_t b, double *
 }
 
 }  // extern "C"
+
+// A(j, i) <- A(i, j) for i > j on the m x m matrix A (lower triangle copied
+// into the upper one), on stream s.
+evd_status_t evd_mirror_lower_f64(hipStream_t s, int64_t m, double *A, int64_t lda)
+{
+    if (m <= 1) return EVD_OK;
+    const dim3 grid((unsigned)evd_ceil_div(m, 32), (unsigned)evd_ceil_div(m, 32));
+    hipLaunchKernelGGL(mirror_lower_kernel<double>, grid, dim3(256), 0, s, m, A, lda);
+    return evd_check_last();
+}
