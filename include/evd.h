@@ -92,6 +92,9 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *                  the 64-sweep BC-back with block reflectors: 1 (eight
  *                  wavefronts; 0 = default) or 2 (four wavefronts, each LDS
  *                  operand feeding two row tiles)
+ *   "bcback_lds2"  1: 64-row workgroups of the 64-sweep BC-back double-buffer
+ *                  their groups in LDS, one workgroup per compute unit;
+ *                  0 (default): one buffer (61 KB), two workgroups per CU
  *   "gemm_staged"  1: every FP64 product stages its K slices through registers;
  *                  0 (default): 128 x 128 tiles with K slices of 16 that are
  *                  all whole load them straight into LDS (same results, bit

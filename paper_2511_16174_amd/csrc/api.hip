@@ -111,6 +111,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "bcback_valu")) return &ctx->bcback_valu;
     if (!strcmp(key, "bcback_sub")) return &ctx->bcback_sub;
     if (!strcmp(key, "bcback_rt")) return &ctx->bcback_rt;
+    if (!strcmp(key, "bcback_lds2")) return &ctx->bcback_lds2;
     if (!strcmp(key, "gemm_staged")) return &ctx->gemm_staged;
     if (!strcmp(key, "orgsb_nb")) return &ctx->orgsb_nb;
     if (!strcmp(key, "batch_streams")) return &ctx->batch_streams;
@@ -139,7 +140,8 @@ evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value)
     if ((slot == &ctx->bcback_group && value != 0 && value != 32 && value != 64) ||
         (slot == &ctx->bcback_rows && value != 0 && value != 64 && value != 128) ||
         (slot == &ctx->bcback_sub && value != 0 && value != 16 && value != 32 && value != 64) ||
-        (slot == &ctx->bcback_rt && value > 2) || (slot == &ctx->gemm_staged && value > 1)) {
+        (slot == &ctx->bcback_rt && value > 2) || (slot == &ctx->gemm_staged && value > 1) ||
+        (slot == &ctx->bcback_lds2 && value > 1)) {
         ctx->last_invalid_arg = 3;
         return EVD_ERR_INVALID_ARG;
     }

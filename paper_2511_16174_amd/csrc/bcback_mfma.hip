@@ -450,8 +450,8 @@ __global__ __launch_bounds__(256) void bct_wide_kernel(int64_t n, int B, const d
 // carries two independent accumulation chains, so one wavefront per SIMD
 // keeps the matrix core fed without a second wavefront to cover LDS latency
 // (and the register file of a SIMD holds the two windows of one wavefront).
-template <int B, int G, int NWV, bool REV, int SG, int RT>
-__global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows, int64_t n,
+template <int B, int G, int NWV, bool REV, int SG, int RT, int NB, int MINB>
+__global__ __launch_bounds__(NWV * 64, MINB) void bcback_wide_kernel(int64_t mrows, int64_t n,
                                                                   const double *__restrict__ V,
                                                                   const double *__restrict__ Tg, int64_t nblk,
                                                                   double *__restrict__ Q, int64_t ldq)
@@ -472,8 +472,9 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
     constexpr int NV = G * B / NTH, NT = TS / NTH;
     constexpr int RW = 16 * RT;   // rows per wavefront
     static_assert(W % 16 == 0 && (G * B) % NTH == 0 && TS % NTH == 0, "tile shapes");
-    __shared__ double Vs[2][VS];
-    __shared__ double Ts[2][TS];
+    static_assert(NB == 1 || NB == 2, "LDS buffers");
+    __shared__ double Vs[NB][VS];
+    __shared__ double Ts[NB][TS];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -495,7 +496,7 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
     const uint32_t loff = ((uint32_t)li + (uint32_t)lk * (uint32_t)ldq) * 8u;
     const int64_t nsweeps = n - 2;
 
-    for (int e = tid; e < 2 * VS; e += NTH) (&Vs[0][0])[e] = 0.0;
+    for (int e = tid; e < NB * VS; e += NTH) (&Vs[0][0])[e] = 0.0;
     __syncthreads();
 
     double gv[NV], gt[NT];
@@ -729,7 +730,7 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
             }
             }  // SG == 0
             if (more) {
-                store_group(buf ^ 1);
+                if constexpr (NB == 2) store_group(buf ^ 1);
                 if (REV) {
 #pragma unroll
                     for (int r = 0; r < RT; ++r) {
@@ -774,8 +775,18 @@ __global__ __launch_bounds__(NWV * 64, 1) void bcback_wide_kernel(int64_t mrows,
                     base -= B;
                 }
             }
-            __syncthreads();
-            buf ^= 1;
+            if constexpr (NB == 1) {
+                // one buffer: the next group is stored once every wavefront
+                // has finished reading the current one
+                if (more) {
+                    __syncthreads();
+                    store_group(0);
+                }
+                __syncthreads();
+            } else {
+                __syncthreads();
+                buf ^= 1;
+            }
         }
         {
             const bool wfull = rows_full && base + W <= n;
@@ -865,11 +876,17 @@ evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t 
         // two 16-row tiles per wavefront (4 wavefronts, 128 rows) when block
         // reflectors are used and "bcback_rt" asks for it
         const bool rt2 = (sub == 16 || sub == 32) && ctx->bcback_rt == 2;
+        // 64-row workgroups with one LDS buffer (61 KB), two per compute unit,
+        // unless "bcback_lds2" asks for the double-buffered single one
+        const bool one_buf = ctx->bcback_lds2 == 0;
         auto launch = [&](bool w8, int64_t r0, int64_t rows) {
             const dim3 grid((unsigned)evd_ceil_div(rows, w8 ? 128 : 64));
             double *Qr = Q + r0;
 #define EVD_BCW(NW, RV, SB, R)                                                                                      \
-    hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, NW, RV, SB, R>), grid, dim3(NW * 64), 0, s, rows, n, V, Tg,   \
+    hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, NW, RV, SB, R, 2, 1>), grid, dim3(NW * 64), 0, s, rows, n, V,  \
+                       Tg, nblk, Qr, ldq)
+#define EVD_BCW1(RV, SB)                                                                                             \
+    hipLaunchKernelGGL((bcback_wide_kernel<64, BC_GW, 4, RV, SB, 1, 1, 2>), grid, dim3(256), 0, s, rows, n, V, Tg,   \
                        nblk, Qr, ldq)
 #define EVD_BCW_SUB(NW, RV)                                                                                          \
     do {                                                                                                             \
@@ -888,10 +905,19 @@ evd_status_t bcback_mfma_apply(evd_ctx_t ctx, int64_t mrows, int64_t n, int64_t 
             } else if (w8) {
                 if (rev) EVD_BCW_SUB(8, true);
                 else EVD_BCW_SUB(8, false);
+            } else if (one_buf && (sub == 16 || sub == 32)) {
+                if (rev) {
+                    if (sub == 16) EVD_BCW1(true, 16);
+                    else EVD_BCW1(true, 32);
+                } else {
+                    if (sub == 16) EVD_BCW1(false, 16);
+                    else EVD_BCW1(false, 32);
+                }
             } else {
                 if (rev) EVD_BCW_SUB(4, true);
                 else EVD_BCW_SUB(4, false);
             }
+#undef EVD_BCW1
 #undef EVD_BCW_RT2
 #undef EVD_BCW_SUB
 #undef EVD_BCW

@@ -190,6 +190,7 @@ struct evd_ctx_s {
     int64_t bcback_valu;      // 1 = reflector-by-reflector BC-back on the vector ALUs (0 = blocked MFMA)
     int64_t bcback_sub;       // sweeps per block reflector inside a 64-sweep group (0 = 32, 16, 32, 64)
     int64_t bcback_rt;        // 16-row tiles per wavefront of the 64-sweep BC-back (0 = 1, 1, 2)
+    int64_t bcback_lds2;      // 1: 64-row BC-back workgroups double-buffered, one per CU (0 = single buffer, two per CU)
     int64_t gemm_staged;      // 1: FP64 GEMM main loop staged through registers everywhere (process-wide; 0 = direct-to-LDS loads for whole tiles)
     int64_t batch_streams;    // streams used by the batched driver (0 = 4)
     int64_t batch_graph;      // 1 = capture the batched launch sequence in a hipGraph

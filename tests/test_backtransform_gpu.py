@@ -86,15 +86,18 @@ def test_bcback_blocked_matches_valu_kernel(n, b, mrows):
 
 
 @pytest.mark.parametrize("trans", ["N", "T"])
-@pytest.mark.parametrize("group,rows,sub,rt", [(32, 0, 0, 0), (64, 64, 0, 0), (64, 128, 0, 0), (64, 64, 16, 0),
-                                               (64, 128, 32, 0), (64, 128, 64, 0), (64, 128, 32, 2), (64, 128, 16, 2),
-                                               (64, 0, 0, 2)])
-def test_bcback_b64_group_and_row_variants(trans, group, rows, sub, rt):
+@pytest.mark.parametrize("group,rows,sub,rt,lds2", [(32, 0, 0, 0, 0), (64, 64, 0, 0, 0), (64, 128, 0, 0, 0),
+                                                    (64, 64, 16, 0, 0), (64, 128, 32, 0, 0), (64, 128, 64, 0, 0),
+                                                    (64, 128, 32, 2, 0), (64, 128, 16, 2, 0), (64, 0, 0, 2, 0),
+                                                    (64, 64, 0, 0, 1), (64, 64, 64, 0, 0)])
+def test_bcback_b64_group_and_row_variants(trans, group, rows, sub, rt, lds2):
     """b = 64: 32- and 64-sweep groups, 64- and 128-row workgroups, 64-sweep
     groups applied whole or as 16- or 32-sweep block reflectors
     ("bcback_sub"), one or two 16-row tiles per wavefront ("bcback_rt"), on a
     size with a ragged last group (n - 2 not a multiple of 64) and partial
-    workgroups and row tiles (m_rows not a multiple of 128 or 32)."""
+    workgroups and row tiles (m_rows not a multiple of 128 or 32); 64-row
+    workgroups with one LDS buffer (two per compute unit, the default) or two
+    ("bcback_lds2")."""
     from paper_2511_16174_amd import evd
     import torch
     ctx = evd.context(0)
@@ -112,6 +115,7 @@ def test_bcback_b64_group_and_row_variants(trans, group, rows, sub, rt):
     ctx.set_param("bcback_rows", rows)
     ctx.set_param("bcback_sub", sub)
     ctx.set_param("bcback_rt", rt)
+    ctx.set_param("bcback_lds2", lds2)
     try:
         ctx.evd_dbcback(trans, mrows, n, b, dV, dT, dX, mrows, work_dev(wb), wb)
         torch.cuda.synchronize()
@@ -120,6 +124,7 @@ def test_bcback_b64_group_and_row_variants(trans, group, rows, sub, rt):
         ctx.set_param("bcback_rows", 0)
         ctx.set_param("bcback_sub", 0)
         ctx.set_param("bcback_rt", 0)
+        ctx.set_param("bcback_lds2", 0)
     out = from_dev(dX, mrows, n)
     assert np.max(np.abs(out - ref)) <= 100 * n * M.EPS * np.abs(X).max()
 
