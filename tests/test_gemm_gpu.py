@@ -117,7 +117,8 @@ def test_dgemm_many_splits_small_outputs(m, n, k, opa, lower, alpha, beta):
     ("N", "T", 1, 2900, 2900, 256, -1.0), ("T", "T", 0, 2950, 2900, 48, 1.0), ("N", "N", 0, 3200, 3200, 4096, 1.0),
     ("N", "N", 0, 2900, 2900, 650, 1.0), ("N", "N", 0, 3000, 64, 3008, 0.0), ("T", "N", 0, 2900, 64, 512, 1.0),
     ("N", "N", 0, 3000, 70, 640, 0.5), ("T", "N", 0, 2900, 64, 1003, 1.0), ("N", "T", 1, 2900, 2900, 77, 0.5),
-    ("T", "T", 0, 2950, 2900, 33, 1.0)])
+    ("T", "T", 0, 2950, 2900, 33, 1.0), ("N", "N", 0, 3000, 64, 16, 1.0), ("N", "N", 0, 3000, 64, 20, 0.5),
+    ("T", "N", 0, 2900, 64, 9, 1.0), ("T", "N", 0, 3000, 64, 32, 0.0), ("N", "N", 0, 4000, 64, 4000, 0.0)])
 def test_dgemm_direct_lds_matches_staged(opa, opb, lower, m, n, k, beta):
     """128 x 128 and 128 x 64 tiles with whole K slices of 16 run the kernel
     whose slices are loaded straight into LDS (tiles crossing the edge of C
@@ -125,7 +126,7 @@ def test_dgemm_direct_lds_matches_staged(opa, opb, lower, m, n, k, beta):
     last slice of K zero-filled); it performs the same products in the same order as the main
     loop staged through registers ("gemm_staged" = 1), so both give the same
     bits; a K split (3200^2 x 4096 with workspace) and the lower-triangle
-    modes included."""
+    modes included; K down to one slice, one and a part, and a part only."""
     from paper_2511_16174_amd import evd
     ctx = evd.context(0)
     rng = np.random.default_rng(m + 3 * n + k)
