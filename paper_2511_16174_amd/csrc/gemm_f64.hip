@@ -35,6 +35,7 @@ constexpr int PAD = 1;
 int g_gemm_swizzle = 1;  // XCD-aware tile order (gemm_tile); not used for triangular outputs, where it was slower
 int g_gemm_cus = 256;    // compute units of the device (set when a context is created)
 int g_gemm_dl = 1;       // direct-to-LDS kernel for 128 x 128 tiles (0: main loop staged through registers)
+constexpr int GEMM_LOWER_BAND = 4;  // tile rows per band of the triangular grids (1: row-major order)
 
 // waves per SIMD to budget registers for: 8-wavefront tiles (two workgroups
 // per CU, four waves per SIMD) fit 128 VGPRs, 4-wavefront tiles 256; the
@@ -227,21 +228,41 @@ __device__ __forceinline__ void gemm_tile(int swz, int &bx, int &by)
     by = r / gsz;
 }
 
-// Tile (bx >= by) of a lower-triangular grid launched as one dimension of
-// T (T + 1) / 2 workgroups: ids made XCD-contiguous as in gemm_tile, then
-// taken in row-major order of the lower triangle.
-__device__ __forceinline__ void gemm_tile_lower(int &bx, int &by)
+// Tile (bx >= by) of a lower-triangular grid of T tile rows launched as one
+// dimension of T (T + 1) / 2 workgroups: ids made XCD-contiguous as in
+// gemm_tile, then taken band by band, a band being G tile rows walked column
+// by column (so a tile column's slice of B serves G tiles in a row from L2);
+// G = 1 is the row-major order of the lower triangle.
+__device__ __forceinline__ void gemm_tile_lower(int &bx, int &by, int G)
 {
     constexpr int XCD = 8;
     const int total = gridDim.x;
     int pid = blockIdx.x;
     const int full = (total / XCD) * XCD;
     if (pid < full) pid = (pid % XCD) * (total / XCD) + pid / XCD;
-    int i = (int)((sqrt(8.0 * (double)pid + 1.0) - 1.0) * 0.5);
-    while (i * (i + 1) / 2 > pid) --i;
-    while ((i + 1) * (i + 2) / 2 <= pid) ++i;
-    bx = i;
-    by = pid - i * (i + 1) / 2;
+    // tiles before band b (all full): C(b) = G^2 b (b - 1) / 2 + b G (G + 1) / 2
+    auto start = [&](int b) { return (G * G * b * (b - 1)) / 2 + b * (G * (G + 1)) / 2; };
+    int b = (int)((sqrt(8.0 * (double)pid + 1.0) - 1.0) / (2.0 * G));
+    while (b > 0 && start(b) > pid) --b;
+    while (start(b + 1) <= pid) ++b;
+    int T = (int)((sqrt(8.0 * (double)total + 1.0) - 1.0) * 0.5);
+    while (T * (T + 1) / 2 > total) --T;
+    while ((T + 1) * (T + 2) / 2 <= total) ++T;
+    const int r0 = b * G, h = (T - r0) < G ? (T - r0) : G;
+    int o = pid - start(b);
+    if (o < h * r0) {  // columns left of the band's diagonal block: h tiles each
+        by = o / h;
+        bx = r0 + o % h;
+        return;
+    }
+    o -= h * r0;  // the band's diagonal block, column jj holding h - jj tiles
+    int jj = 0;
+    while (o >= h - jj) {
+        o -= h - jj;
+        ++jj;
+    }
+    by = r0 + jj;
+    bx = r0 + jj + o;
 }
 
 template <int BM, int BN, int WM, int WN, int OPA, int OPB, int LOWER>
@@ -251,7 +272,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, gemm_min_waves(BM, BN, 
     int64_t split_stride, int swz)
 {
     int bx, by;
-    if (LOWER && BM == BN && swz == 2) gemm_tile_lower(bx, by);  // triangular grid
+    if (LOWER && BM == BN && swz >= 2) gemm_tile_lower(bx, by, swz - 1);  // triangular grid
     else gemm_tile(swz, bx, by);
     const int64_t m0 = (int64_t)bx * BM, n0 = (int64_t)by * BN;
     if (LOWER && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
@@ -442,7 +463,7 @@ __global__ __launch_bounds__(512, gemm_min_waves(128, BN, BN == 128 ? 64 : 32, 3
 {
     __shared__ double smem[dl_lds_elems<BN>()];
     int bx, by;
-    if (LOWER && swz == 2) gemm_tile_lower(bx, by);
+    if (LOWER && swz >= 2) gemm_tile_lower(bx, by, swz - 1);
     else gemm_tile(swz, bx, by);
     const int64_t mlo = (int64_t)bx * 128, nlo = (int64_t)by * BN;
     if (LOWER && nlo > mlo + 127) return;  // tile strictly above the diagonal
@@ -535,7 +556,7 @@ void launch_cfg(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64
     if (LOWER && BM == BN && grid.z == 1 && m == n) {
         const unsigned T = grid.x;
         grid = dim3(T * (T + 1) / 2, 1, 1);
-        swz = 2;
+        swz = 1 + GEMM_LOWER_BAND;
     }
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, OPA, OPB, LOWER>), grid, dim3(NT), 0, s, m, n, k, kchunk,
                        alpha, A, lda, B, ldb, beta, C, ldc, split_stride, swz);
@@ -551,7 +572,7 @@ void launch_dl(hipStream_t s, dim3 grid, int64_t m, int64_t n, int64_t k, int64_
     if (LOWER && grid.z == 1 && m == n) {
         const unsigned T = grid.x;
         grid = dim3(T * (T + 1) / 2, 1, 1);
-        swz = 2;
+        swz = 1 + GEMM_LOWER_BAND;
     }
     hipLaunchKernelGGL((gemm_f64_dl_kernel<OPA, OPB, LOWER, BN>), grid, dim3(512), 0, s, m, n, k, kchunk, alpha, A, lda, B,
                        ldb, beta, C, ldc, split_stride, swz);
