@@ -273,9 +273,43 @@ __global__ __launch_bounds__(PREP_T) void dc_prep_kernel(int64_t n, int t, const
     }
 }
 
-// Qp[:, destCol[u]] = Z[:, srcCol[u]] for the node block, then the deflation
-// rotations in order; one thread per row.
+// Columns of a node block per workgroup of the column copies (grid z): the
+// copies of a large node are spread over the whole chip instead of one
+// thread per row walking every column.
+constexpr int DC_CC = 256;
+
+// Qp[:, destCol[u]] = Z[:, srcCol[u]] for the node block: thread per row,
+// workgroup z for columns [z DC_CC, (z + 1) DC_CC), eight loads in flight.
 __global__ __launch_bounds__(256) void dc_qp_kernel(int64_t n, int t, const double *Z, int64_t ldz, DcArrays a)
+{
+    const int64_t i = blockIdx.y;
+    int64_t lo, mid, hi;
+    node_range(n, t, i, &lo, &mid, &hi);
+    const int *info = a.info + i * 8;
+    if (!info[6]) return;
+    const int64_t s = hi - lo;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t u0 = (int64_t)blockIdx.z * DC_CC;
+    if (r >= s || u0 >= s) return;
+    const int64_t u1 = (u0 + DC_CC < s) ? u0 + DC_CC : s;
+    const int64_t ld = n;
+    const double *Zr = Z + lo + r + lo * ldz;
+    double *Qr = a.Qp + lo + r + lo * ld;
+    const int *src = a.srcCol + lo, *dst = a.destCol + lo;
+    int64_t u = u0;
+    for (; u + 8 <= u1; u += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = Zr[(int64_t)src[u + q] * ldz];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Qr[(int64_t)dst[u + q] * ld] = v[q];
+    }
+    for (; u < u1; ++u) Qr[(int64_t)dst[u] * ld] = Zr[(int64_t)src[u] * ldz];
+}
+
+// The deflation rotations on Qp, in order; one thread per row (after the
+// column copies of dc_qp_kernel).
+__global__ __launch_bounds__(256) void dc_rot_kernel(int64_t n, int t, DcArrays a)
 {
     const int64_t i = blockIdx.y;
     int64_t lo, mid, hi;
@@ -286,9 +320,7 @@ __global__ __launch_bounds__(256) void dc_qp_kernel(int64_t n, int t, const doub
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= s) return;
     const int64_t ld = n;
-    const double *Zr = Z + lo + r + lo * ldz;
     double *Qr = a.Qp + lo + r + lo * ld;
-    for (int64_t u = 0; u < s; ++u) Qr[(int64_t)a.destCol[lo + u] * ld] = Zr[(int64_t)a.srcCol[lo + u] * ldz];
     const int nrot = info[4];
     for (int k = 0; k < nrot; ++k) {
         const int64_t ca = a.destCol[lo + a.rotP[lo + k]], cb = a.destCol[lo + a.rotI[lo + k]];
@@ -520,7 +552,8 @@ __global__ __launch_bounds__(256) void dc_rank_kernel(int64_t n, int t, DcArrays
     a.outSrc[lo + pos] = (int)q;
 }
 
-// Z block column p <- product column (src < K) or deflated Qp column (src >= K).
+// Z block column p <- product column (src < K) or deflated Qp column (src >= K);
+// thread per row, workgroup z for columns [z DC_CC, (z + 1) DC_CC).
 __global__ __launch_bounds__(256) void dc_scatter_kernel(int64_t n, int t, double *Z, int64_t ldz, DcArrays a)
 {
     const int64_t i = blockIdx.y;
@@ -531,15 +564,27 @@ __global__ __launch_bounds__(256) void dc_scatter_kernel(int64_t n, int t, doubl
     const int64_t s = hi - lo;
     const int K = info[0];
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= s) return;
+    const int64_t p0 = (int64_t)blockIdx.z * DC_CC;
+    if (r >= s || p0 >= s) return;
+    const int64_t p1 = (p0 + DC_CC < s) ? p0 + DC_CC : s;
     const int64_t ld = n;
     const double *Tr = a.Tmp + lo + r + lo * ld;
     const double *Qr = a.Qp + lo + r + lo * ld;
     double *Zr = Z + lo + r + lo * ldz;
-    for (int64_t p = 0; p < s; ++p) {
-        const int src = a.outSrc[lo + p];
-        Zr[p * ldz] = (src < K) ? Tr[(int64_t)src * ld] : Qr[(int64_t)src * ld];
+    const int *osrc = a.outSrc + lo;
+    auto col = [&](int64_t p) {
+        const int src = osrc[p];
+        return (src < K) ? Tr[(int64_t)src * ld] : Qr[(int64_t)src * ld];
+    };
+    int64_t p = p0;
+    for (; p + 8 <= p1; p += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = col(p + q);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Zr[(p + q) * ldz] = v[q];
     }
+    for (; p < p1; ++p) Zr[p * ldz] = col(p);
 }
 
 // ---------------------------------------------------------------- eigenvalues only
@@ -701,8 +746,11 @@ evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const
         const int64_t M = (int64_t)1 << t;
         const int64_t smax = evd_ceil_div(n, M);
         hipLaunchKernelGGL(dc_prep_kernel, dim3((unsigned)M), dim3(PREP_T), 0, s, n, t, e, (const double *)Z, ldz, a);
-        hipLaunchKernelGGL(dc_qp_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M), dim3(256), 0, s, n, t,
-                           (const double *)Z, ldz, a);
+        const unsigned cz = (unsigned)evd_ceil_div(smax, DC_CC);
+        hipLaunchKernelGGL(dc_qp_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M, cz), dim3(256), 0, s, n,
+                           t, (const double *)Z, ldz, a);
+        hipLaunchKernelGGL(dc_rot_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M), dim3(256), 0, s, n, t,
+                           a);
         // lanes per root: enough roots in flight, at least ~32 poles per lane
         int L = 1;
         while (L < 64 && (int64_t)L * 64 <= smax) L *= 2;
@@ -713,8 +761,8 @@ evd_status_t dc_run(evd_ctx_t ctx, char compz, int64_t n, const double *d, const
         EVD_CHECK(gemm_f64_grouped(s, a.probs, (int)(2 * M), smax, smax));
         hipLaunchKernelGGL(dc_rank_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M), dim3(256), 0, s, n,
                            t, a);
-        hipLaunchKernelGGL(dc_scatter_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M), dim3(256), 0, s,
-                           n, t, Z, ldz, a);
+        hipLaunchKernelGGL(dc_scatter_kernel, dim3((unsigned)evd_ceil_div(smax, 256), (unsigned)M, cz), dim3(256), 0,
+                           s, n, t, Z, ldz, a);
         EVD_CHECK(evd_check_last());
     }
     hipLaunchKernelGGL(dc_copy_kernel, grid1(n), dim3(256), 0, s, n, (const double *)a.Dw, W);
