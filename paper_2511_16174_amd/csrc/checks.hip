@@ -23,16 +23,21 @@ __global__ void nf_clear_kernel(int *flag)
 }
 
 // Workgroups stride over columns, threads over the rows of the referenced
-// part of a column; the flag is written only by workgroups that met a
-// non-finite entry, once each.
+// part of a column, four loads in flight per thread; the flag is written only
+// by workgroups that met a non-finite entry, once each.
 __global__ __launch_bounds__(256) void nf_scan_kernel(int64_t n, const double *A, int64_t lda, int upper, int *flag)
 {
     int bad = 0;
     for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
         const double *col = A + j * lda;
         const int64_t i0 = upper ? 0 : j, i1 = upper ? j + 1 : n;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
-            if (!isfinite(col[i])) bad = 1;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += 4 * blockDim.x) {
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = (i + q * blockDim.x < i1) ? col[i + q * blockDim.x] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bad |= isfinite(v[q]) ? 0 : 1;
+        }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
 }

@@ -271,6 +271,20 @@ def test_nonfinite_input_reports_status(n, jobz, bad):
     check(B, w, Q, oracle.syev(B, jobz="N"))
 
 
+@pytest.mark.parametrize("row,col", [(2999, 5), (2000, 1000), (1300, 1000), (1600, 1000), (1029, 5), (2999, 2998)])
+def test_nonfinite_deep_in_a_long_column(row, col):
+    """Entries at every position of the scan's four loads in flight per
+    thread and past its first round of 1024 rows."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    n = 3000
+    A = W.gaussian_sym(n, seed=45)
+    A[row, col] = np.inf
+    w, _, info = raw_dsyevd(ctx, A, jobz="N", uplo="L")
+    assert info == evd.EVD_ERR_NONFINITE
+    assert np.all(np.isnan(w))
+
+
 @pytest.mark.parametrize("uplo", ["L", "U"])
 def test_nonfinite_entries_outside_the_referenced_triangle_are_ignored(uplo):
     from paper_2511_16174_amd import evd
