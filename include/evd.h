@@ -76,6 +76,10 @@ evd_status_t evd_set_stream(evd_ctx_t ctx, void *stream);
  *   "panel_wgs"    0 (default) = each panel-QR workgroup holds as many rows
  *                  as its registers take (512 at b = 64), the fewest
  *                  workgroups; k > 0 = the rows spread over about k workgroups
+ *   "panel_generic" 1: b = 64 panels in the generic thread layout (eight
+ *                  lanes of a wavefront per column); 0 (default): each
+ *                  wavefront holds eight whole columns over 64 rows per lane
+ *                  step (the sums are formed in another order)
  *   "bcback_valu"  1 = apply the bulge-chasing reflectors one by one on the
  *                  vector ALUs; 0 (default) = in compact-WY groups of sweeps on
  *                  the matrix cores (b = 16, 32, 64)

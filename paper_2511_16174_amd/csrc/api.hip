@@ -107,6 +107,7 @@ static int64_t *param_slot(evd_ctx_t ctx, const char *key)
     if (!strcmp(key, "order")) return &ctx->order;
     if (!strcmp(key, "timing")) return &ctx->timing;
     if (!strcmp(key, "panel_wgs")) return &ctx->panel_wgs;
+    if (!strcmp(key, "panel_generic")) return &ctx->panel_generic;
     if (!strcmp(key, "sbr_nb")) return &ctx->sbr_nb;
     if (!strcmp(key, "bcback_valu")) return &ctx->bcback_valu;
     if (!strcmp(key, "bcback_sub")) return &ctx->bcback_sub;
@@ -141,7 +142,7 @@ evd_status_t evd_set_param(evd_ctx_t ctx, const char *key, int64_t value)
         (slot == &ctx->bcback_rows && value != 0 && value != 64 && value != 128) ||
         (slot == &ctx->bcback_sub && value != 0 && value != 16 && value != 32 && value != 64) ||
         (slot == &ctx->bcback_rt && value > 2) || (slot == &ctx->gemm_staged && value > 1) ||
-        (slot == &ctx->bcback_lds2 && value > 1)) {
+        (slot == &ctx->bcback_lds2 && value > 1) || (slot == &ctx->panel_generic && value > 1)) {
         ctx->last_invalid_arg = 3;
         return EVD_ERR_INVALID_ARG;
     }

@@ -185,6 +185,7 @@ struct evd_ctx_s {
     int64_t last_tuned_nb;    // choices of the last evd_autotune call (read only)
     int64_t last_tuned_sub;
     int64_t panel_wgs;        // panel-QR rows spread over about this many workgroups (0 = fewest)
+    int64_t panel_generic;    // 1: b = 64 panels in the generic layout (0 = column layout)
     int64_t sbr_nb;           // SBR outer block in columns (0 = 320; <= b: single blocking)
     int64_t orgsb_nb;         // SBR-back reflector group in columns (0 = 512)
     int64_t bcback_valu;      // 1 = reflector-by-reflector BC-back on the vector ALUs (0 = blocked MFMA)

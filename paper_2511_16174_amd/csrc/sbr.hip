@@ -437,6 +437,258 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_qr_kernel(int64_t m, int 
     for (int e = tid; e < B * B; e += PANEL_THREADS) Tout[e] = Ts[e];
 }
 
+// B = 64 with a column layout: wavefront w holds columns 8w .. 8w+7 of the
+// workgroup's rows, lane l the rows l + 64 t (t < 8).  A wavefront's LDS read
+// of the pivot column then touches 64 different rows (the layout above has
+// eight lanes of a wavefront read each entry), and the entries a thread reads
+// feed the products of its eight columns (and, read once more, their
+// update).  A column's sum over the rows is a reduction across the wavefront:
+// a reduce-scatter (exchanges with lanes 32, 16 and 8 apart, after which the
+// lanes that agree in bits 3..5 hold one column each) and a butterfly over
+// the last eight lanes.  The records, the Householder scalars, Y and T are
+// formed as in panel_qr_kernel; only the order of the sums differs.
+constexpr int P64_CPW = 8;    // columns per wavefront
+constexpr int P64_RR = 8;     // rows per lane and column
+constexpr int P64_CH = 64 * P64_RR;  // rows per workgroup at most
+
+template <typename T>
+__global__ __launch_bounds__(PANEL_THREADS) void panel_qr64_kernel(int64_t m, int chunk, T *P, int64_t lda,
+                                                                   T *Y1, T *Y2, int64_t ldy, T *part,
+                                                                   T *Sg, T *taus, T *Tout,
+                                                                   T *AB, int64_t ldab, int64_t j0, int epoch0,
+                                                                   int *err)
+{
+    constexpr int B = 64, NWV = PANEL_THREADS / 64, CPW = P64_CPW, RR = P64_RR;
+    static_assert(NWV * CPW == B, "eight wavefronts of eight columns");
+    __shared__ T colbuf2[2][P64_CH];
+    __shared__ T scr[NWV * B];
+    __shared__ T Ts[B * B];
+    __shared__ T hsh[B];
+    __shared__ T topsh[B];
+    __shared__ T scales[B];
+    __shared__ T betas[B];
+
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t r0 = (int64_t)g * chunk;
+    const int rows = (int)((m - r0) < chunk ? (m - r0) : chunk);
+    const int nr = (int)(m < B ? m : B);
+    // the column whose sum this lane holds after the reduction
+    const int cl = 4 * ((lane >> 5) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 3) & 1);
+
+    T x[CPW][RR];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int t = 0; t < RR; ++t) {
+            const int i = lane + 64 * t;
+            x[c][t] = (i < rows) ? P[(r0 + i) + (int64_t)(CPW * w + c) * lda] : (T)0;
+        }
+
+    for (int j = 0; j < nr; ++j) {
+        const int E = epoch0 + j + 1;
+        uint64_t *rec = (uint64_t *)part + (size_t)(j & 1) * PANEL_MAX_WGS * 2 * B * LL_WORDS<T>;
+        const int jl = (int)(j - r0);  // local index of row j (0 .. 63 in workgroup 0, negative elsewhere)
+        T *colbuf = colbuf2[j & 1];
+        // ---- (1) pivot column to LDS; every thread reads its rows of it
+        if (w == j / CPW) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+                if (c == j % CPW) {
+#pragma unroll
+                    for (int t = 0; t < RR; ++t) colbuf[lane + 64 * t] = x[c][t];
+                }
+        }
+        __syncthreads();
+        T pv[RR];
+#pragma unroll
+        for (int t = 0; t < RR; ++t) pv[t] = colbuf[lane + 64 * t];
+        // rows <= j can only be local rows 0 .. 63 of workgroup 0 (t = 0)
+        const T p0 = (lane > jl) ? pv[0] : (T)0;
+        T acc[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            T a = p0 * x[c][0];
+#pragma unroll
+            for (int t = 1; t < RR; ++t) a += pv[t] * x[c][t];
+            acc[c] = a;
+        }
+        // ---- reduce-scatter over the wavefront, then the last eight lanes
+        T a4[4], a2[2];
+        {
+            const bool h = (lane & 32) != 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T send = h ? acc[k] : acc[k + 4];
+                a4[k] = (h ? acc[k + 4] : acc[k]) + __shfl_xor(send, 32, 64);
+            }
+        }
+        {
+            const bool h = (lane & 16) != 0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const T send = h ? a4[k] : a4[k + 2];
+                a2[k] = (h ? a4[k + 2] : a4[k]) + __shfl_xor(send, 16, 64);
+            }
+        }
+        T a1;
+        {
+            const bool h = (lane & 8) != 0;
+            const T send = h ? a2[0] : a2[1];
+            a1 = (h ? a2[1] : a2[0]) + __shfl_xor(send, 8, 64);
+        }
+        a1 += __shfl_xor(a1, 4, 64);
+        a1 += __shfl_xor(a1, 2, 64);
+        a1 += __shfl_xor(a1, 1, 64);
+        const int q = CPW * w + cl;
+        const bool holds_row_j = (g == 0) && (lane == jl) && (jl < rows);
+        if (G == 1) {
+            if ((lane & 7) == 0) hsh[q] = a1;
+            if (holds_row_j) {
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) topsh[CPW * w + c] = x[c][0];
+            }
+        } else {
+            if ((lane & 7) == 0) ll_store(&rec[((size_t)g * 2 * B + q) * LL_WORDS<T>], a1, (uint32_t)E);
+            if (holds_row_j) {
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+                    ll_store(&rec[((size_t)B + CPW * w + c) * LL_WORDS<T>], x[c][0], (uint32_t)E);
+            }
+            // ---- (2) every record of this column, summed: wavefront w reads
+            // records h = w, w + NWV, ... whole (lane q entry q, eight records
+            // in flight, those not yet written polled again); the NWV partial
+            // sums per entry are added in wavefront order
+            T s2 = 0.0;
+            for (int h0 = w; h0 < G; h0 += 8 * NWV) {
+                uint64_t wd[8][LL_WORDS<T>];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int h = h0 + u * NWV;
+#pragma unroll
+                    for (int k = 0; k < LL_WORDS<T>; ++k)
+                        wd[u][k] = (h < G) ? ld_coh(&rec[((size_t)h * 2 * B + lane) * LL_WORDS<T> + k])
+                                           : ll_word(0u, (uint32_t)E);
+                }
+                bool ok = false;
+                for (int it = 0; it < LL_SPIN_MAX && !ok; ++it) {
+                    ok = true;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int h = h0 + u * NWV;
+#pragma unroll
+                        for (int k = 0; k < LL_WORDS<T>; ++k) {
+                            if (ll_epoch(wd[u][k]) != (uint32_t)E) {
+                                ok = false;
+                                wd[u][k] = ld_coh(&rec[((size_t)h * 2 * B + lane) * LL_WORDS<T> + k]);
+                            }
+                        }
+                    }
+                    if (!ok) __builtin_amdgcn_s_sleep(1);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s2 += ll_value<T>(wd[u]);
+                if (!ok) {  // never written: poison, report, do not hang
+                    s2 = (T)__builtin_nan("");
+                    st_coh(err, 2);
+                }
+            }
+            scr[w * B + lane] = s2;
+            if (tid < B) topsh[tid] = ll_load<T>(&rec[((size_t)B + tid) * LL_WORDS<T>], (uint32_t)E, err);
+            __syncthreads();
+            if (tid < B) {
+                T r = 0.0;
+#pragma unroll
+                for (int u = 0; u < NWV; ++u) r += scr[u * B + tid];
+                hsh[tid] = r;
+            }
+        }
+        __syncthreads();
+        // ---- (3) Householder vector of column j: v = (x - beta e_j) / (x_j - beta)
+        const T x0 = topsh[j], sig = hsh[j];
+        T tau = 0.0, beta = x0, scale = 0.0;
+        if (sig != 0.0) {
+            const T nrm = sqrt(x0 * x0 + sig);
+            beta = (x0 >= 0.0) ? -nrm : nrm;
+            tau = (beta - x0) / beta;
+            scale = 1.0 / (x0 - beta);
+        }
+        if (tid == 0) {
+            scales[j] = scale;
+            betas[j] = beta;
+            if (g == 0) taus[j] = tau;
+        }
+        // Y(:, q)^T v_j for q < j, with column q's own scale applied
+        if (g == 0 && tid < j) Sg[tid + (int64_t)j * B] = scales[tid] * (topsh[tid] + scale * hsh[tid]);
+        if (tau != 0.0) {
+            // rows i >= j of column q > j: P(i, q) -= v_i tau (v_j^T P(:, q));
+            // the pivot entries read again (not kept across the exchange:
+            // registers)
+            T v[RR];
+#pragma unroll
+            for (int t = 0; t < RR; ++t) v[t] = colbuf[lane + 64 * t];
+            v[0] = (lane == jl) ? (T)1 : ((lane > jl) ? scale * v[0] : (T)0);
+#pragma unroll
+            for (int t = 1; t < RR; ++t) v[t] = scale * v[t];
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+                const int qc = CPW * w + c;
+                if (qc > j) {
+                    const T cf = tau * (topsh[qc] + scale * hsh[qc]);
+#pragma unroll
+                    for (int t = 0; t < RR; ++t) x[c][t] -= v[t] * cf;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- write back: explicit Y into the panel of A and into the two
+    // accumulator slots of the outer block
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int qc = CPW * w + c;
+#pragma unroll
+        for (int t = 0; t < RR; ++t) {
+            const int i = lane + 64 * t;
+            if (i < rows) {
+                const int64_t gi = r0 + i;
+                T y = 0.0;
+                if (qc < nr) y = (gi > qc) ? scales[qc] * x[c][t] : (gi == qc ? (T)1 : (T)0);
+                P[gi + (int64_t)qc * lda] = y;
+                Y1[gi + (int64_t)qc * ldy] = y;
+                Y2[gi + (int64_t)qc * ldy] = y;
+            }
+        }
+    }
+    if (g != 0) return;
+    // R (upper trapezoid of the first nr rows) -> band storage: row p = lane
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int qc = CPW * w + c;
+        if (lane <= qc) {
+            const T v = (lane >= nr) ? (T)0 : ((lane == qc) ? betas[qc] : x[c][0]);
+            AB[(B + lane - qc) + (j0 + qc) * ldab] = v;
+        }
+    }
+    // T factor in LDS, then out: column j: T[0:j, j] = -tau_j T[0:j, 0:j] Sg[0:j, j];
+    // row p of the product split over the TPC adjacent threads of row p
+    constexpr int TPC = PANEL_THREADS / B;
+    for (int e = tid; e < B * B; e += PANEL_THREADS) Ts[e] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < B; ++j) {
+        const T tj = (j < nr) ? taus[j] : 0.0;
+        const int pr = tid / TPC, u = tid % TPC;
+        T s = 0.0;
+        if (pr < j)
+            for (int r = pr + u; r < j; r += TPC) s += Ts[pr + r * B] * Sg[r + (int64_t)j * B];
+        s = lane_group_sum<TPC>(s);
+        if (pr < j && u == 0) Ts[pr + j * B] = -tj * s;
+        if (tid == 0) Ts[j + j * B] = tj;
+        __syncthreads();
+    }
+    for (int e = tid; e < B * B; e += PANEL_THREADS) Tout[e] = Ts[e];
+}
+
 template <int B, typename T>
 evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T *Y2, int64_t ldy, T *part,
                           T *Sg, T *taus, T *Tout, T *AB, int64_t ldab, int64_t j0, int epoch0, int *err)
@@ -465,11 +717,14 @@ evd_status_t launch_panel(evd_ctx_t ctx, int64_t m, T *P, int64_t lda, T *Y1, T 
     // most PANEL_MAX_WGS workgroups find free compute units: the previous
     // kernels of the stream have finished and bulge chasing holds at most
     // "bc_waves" of them); its record polls are bounded either way
+    // B = 64: the column layout (chunk <= 512 rows always holds at B = 64)
+    const void *kern = (const void *)panel_qr_kernel<B, T>;
+    if constexpr (B == 64)
+        if (!ctx->panel_generic && chunk <= P64_CH) kern = (const void *)panel_qr64_kernel<T>;
     hipError_t e = ctx->plain_panels
-                       ? hipLaunchKernel((const void *)panel_qr_kernel<B, T>, dim3((unsigned)G), dim3(PANEL_THREADS),
-                                         args, lds, ctx->stream)
-                       : hipLaunchCooperativeKernel((const void *)panel_qr_kernel<B, T>, dim3((unsigned)G),
-                                                    dim3(PANEL_THREADS), args, (unsigned)lds, ctx->stream);
+                       ? hipLaunchKernel(kern, dim3((unsigned)G), dim3(PANEL_THREADS), args, lds, ctx->stream)
+                       : hipLaunchCooperativeKernel(kern, dim3((unsigned)G), dim3(PANEL_THREADS), args, (unsigned)lds,
+                                                    ctx->stream);
     return evd_hip(ctx, e);
 }
 

@@ -62,7 +62,8 @@ def test_params(vctx):
     assert lib.evd_last_invalid_arg(h) == 3
     for key, good, bad in ((b"bcback_group", (0, 32, 64), (16, 48)), (b"bcback_rows", (0, 64, 128), (32, 96)),
                            (b"bcback_sub", (0, 16, 32, 64), (8, 48)), (b"bcback_rt", (0, 1, 2), (3, 4)),
-                           (b"gemm_staged", (0, 1), (2, 5)), (b"bcback_lds2", (0, 1), (2, 3))):
+                           (b"gemm_staged", (0, 1), (2, 5)), (b"bcback_lds2", (0, 1), (2, 3)),
+                           (b"panel_generic", (0, 1), (2, 3))):
         for v in good:
             assert lib.evd_set_param(h, key, v) == evd.EVD_OK
         for v in bad:

@@ -130,3 +130,35 @@ def test_sbr_panel_row_slices(n, b, wgs):
     assert M.orthogonality(Q) <= 10
     rec = np.linalg.norm(Q @ B @ Q.T - A) / (n * np.linalg.norm(A) * M.EPS)
     assert rec <= 10
+
+
+@pytest.mark.parametrize("n,wgs", [(66, 0), (67, 0), (130, 0), (300, 0), (1100, 0), (1100, 16), (2500, 0)])
+def test_sbr_panel_column_layout_matches_generic(n, wgs):
+    """b = 64 panels in the column layout (default: each wavefront holds eight
+    whole columns) and in the generic layout ("panel_generic" = 1) give the
+    same band up to the order of the sums, both reconstruct A, and the
+    column layout is reproducible bit for bit; panels shorter than b (n = 67),
+    partial last workgroups and rows spread over 15 workgroups included."""
+    from paper_2511_16174_amd import evd
+    ctx = evd.context(0)
+    b = 64
+    A = W.gaussian_sym(n, seed=3 * n + wgs)
+    try:
+        ctx.set_param("panel_wgs", wgs)
+        AB1, Aout1, T1, p = run_sbr(A, b)
+        AB1b, _, _, _ = run_sbr(A, b)
+        ctx.set_param("panel_generic", 1)
+        AB2, Aout2, T2, _ = run_sbr(A, b)
+    finally:
+        ctx.set_param("panel_wgs", 0)
+        ctx.set_param("panel_generic", 0)
+    assert np.array_equal(AB1, AB1b)
+    ldab = 2 * b + 1
+    B1 = band_to_dense(AB1, n, b, ldab)
+    B2 = band_to_dense(AB2, n, b, ldab)
+    assert np.abs(B1 - B2).max() <= 1e-11 * np.abs(A).max() * n
+    for Aout, T, B in ((Aout1, T1, B1), (Aout2, T2, B2)):
+        Q = q_from_panels(Aout, T, n, b, p)
+        assert M.orthogonality(Q) <= 10
+        rec = np.linalg.norm(Q @ B @ Q.T - A) / (n * np.linalg.norm(A) * M.EPS)
+        assert rec <= 10
