@@ -274,7 +274,7 @@ def test_nonfinite_input_reports_status(n, jobz, bad):
 @pytest.mark.parametrize("row,col", [(2999, 5), (2000, 1000), (1300, 1000), (1600, 1000), (1029, 5), (2999, 2998)])
 def test_nonfinite_deep_in_a_long_column(row, col):
     """Entries at every position of the scan's four loads in flight per
-    thread and past its first round of 1024 rows."""
+    thread and past its first pass over 1024 rows."""
     from paper_2511_16174_amd import evd
     ctx = evd.context(0)
     n = 3000
